@@ -1,0 +1,143 @@
+/*
+ * CPU oracle for top-down BFS — TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+ * load this file's library. The GPU product path never calls it and shares no
+ * code with it: no headers, no helpers, no tables.
+ *
+ * What it computes (plain C, int32 / int64 integers, no floating point):
+ *
+ *   oracle_bfs       The textbook serial FIFO-queue BFS (paper section 3: a
+ *                    queue with constant-time enqueue/dequeue, O(V+E)), written
+ *                    in the shape of the serial top-down algorithm (section 3.1,
+ *                    Algorithm 1): every vertex starts with no predecessor, the
+ *                    source is its own predecessor, each dequeued vertex scans
+ *                    its whole neighbour list and every not-yet-visited
+ *                    neighbour is marked visited, recorded with the dequeued
+ *                    vertex as predecessor and queued.
+ *                    levels[v] is the layer index of v (section 3: a layer is
+ *                    the set of vertices at the same distance from the source,
+ *                    distance counted in edges); unreached vertices get -1 in
+ *                    both arrays (the paper's "infinity" predecessor, read as -1).
+ *                    Because levels[] is a hop distance it is unique, so the GPU
+ *                    path must reproduce it exactly. parents[] is not unique
+ *                    (section 3.2: different correct BFS trees can result), so
+ *                    the oracle's FIFO-first parent is never compared directly;
+ *                    oracle_validate checks a candidate tree instead.
+ *
+ *   oracle_validate  Complete check of a candidate (levels, parents) against the
+ *                    oracle's levels: V1 levels identical; V2 root is level 0 and
+ *                    its own parent; V3 level -1 exactly where parent -1; V4 every
+ *                    other reached vertex has a parent in range, one level up,
+ *                    joined to it by an arc parent -> vertex.
+ *
+ * Pins: tests/test_oracle_*.py check this file against brute force on every
+ * labelled graph with n <= 6, unit-weight Bellman-Ford on random digraphs,
+ * closed forms (path, cycle, star, complete graph, grid, binary tree, disjoint
+ * components) and the paper's worked examples.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+
+enum { ORACLE_OK = 0, ORACLE_E_ARG = -1, ORACLE_E_ROOT = -3, ORACLE_E_MEM = -4 };
+
+/*
+ * stats (nullable) receives: [0] R reached vertices, [1] A arcs scanned
+ * (sum of out-degrees of reached vertices), [2] L number of non-empty layers.
+ */
+int oracle_bfs(int64_t n, const int64_t* offsets, const int32_t* cols, int64_t root,
+               int32_t* levels, int32_t* parents, int64_t* stats) {
+    if (n < 1 || !offsets || !levels || !parents) return ORACLE_E_ARG;
+    if (root < 0 || root >= n) return ORACLE_E_ROOT;
+
+    int32_t* queue = (int32_t*)malloc((size_t)n * sizeof(int32_t));
+    if (!queue) return ORACLE_E_MEM;
+
+    for (int64_t v = 0; v < n; ++v) {
+        levels[v] = -1;
+        parents[v] = -1;
+    }
+    levels[root] = 0;
+    parents[root] = (int32_t)root;
+    int64_t head = 0, tail = 0;
+    queue[tail++] = (int32_t)root;
+
+    int64_t arcs = 0;
+    while (head < tail) {
+        int32_t u = queue[head++];
+        int64_t begin = offsets[u], end = offsets[u + 1];
+        arcs += end - begin;
+        for (int64_t j = begin; j < end; ++j) {
+            int32_t v = cols[j];
+            if (levels[v] == -1) { /* not visited */
+                levels[v] = levels[u] + 1;
+                parents[v] = u;
+                queue[tail++] = v;
+            }
+        }
+    }
+    if (stats) {
+        stats[0] = tail;
+        stats[1] = arcs;
+        stats[2] = (int64_t)levels[queue[tail - 1]] + 1;
+    }
+    free(queue);
+    return ORACLE_OK;
+}
+
+/* Does row u contain v? Binary search when rows are sorted, else a scan. */
+static int has_arc(const int64_t* offsets, const int32_t* cols, int64_t u, int32_t v, int sorted) {
+    int64_t lo = offsets[u], hi = offsets[u + 1];
+    if (!sorted) {
+        for (int64_t j = lo; j < hi; ++j)
+            if (cols[j] == v) return 1;
+        return 0;
+    }
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (cols[mid] < v)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo < offsets[u + 1] && cols[lo] == v;
+}
+
+/*
+ * Returns 0 when the candidate passes V1-V4, otherwise the number (1..4) of the
+ * first failing check; *bad_vertex (nullable) receives the offending vertex.
+ * Negative returns are argument errors.
+ */
+int oracle_validate(int64_t n, const int64_t* offsets, const int32_t* cols, int64_t root,
+                    const int32_t* ref_levels, const int32_t* levels, const int32_t* parents,
+                    int rows_sorted, int64_t* bad_vertex) {
+    if (n < 1 || !offsets || !ref_levels || !levels || !parents) return ORACLE_E_ARG;
+    if (root < 0 || root >= n) return ORACLE_E_ROOT;
+    if (bad_vertex) *bad_vertex = -1;
+    for (int64_t v = 0; v < n; ++v) { /* V1 */
+        if (levels[v] != ref_levels[v]) {
+            if (bad_vertex) *bad_vertex = v;
+            return 1;
+        }
+    }
+    if (levels[root] != 0 || parents[root] != root) { /* V2 */
+        if (bad_vertex) *bad_vertex = root;
+        return 2;
+    }
+    for (int64_t v = 0; v < n; ++v) { /* V3 */
+        if ((levels[v] == -1) != (parents[v] == -1)) {
+            if (bad_vertex) *bad_vertex = v;
+            return 3;
+        }
+    }
+    for (int64_t v = 0; v < n; ++v) { /* V4 */
+        if (v == root || levels[v] == -1) continue;
+        int64_t u = parents[v];
+        if (u < 0 || u >= n || levels[u] != levels[v] - 1 ||
+            !has_arc(offsets, cols, u, (int32_t)v, rows_sorted)) {
+            if (bad_vertex) *bad_vertex = v;
+            return 4;
+        }
+    }
+    return 0;
+}

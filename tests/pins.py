@@ -1,0 +1,235 @@
+"""Independent checks that pin the CPU oracle (and, through it, the GPU path).
+
+Every function here takes the oracle's ctypes library handle so that the same
+checks can be re-run against deliberately mutated copies of the oracle source
+(``test_oracle_mutants.py``): a pin set that lets a plausible mistake through is
+itself a test failure.
+
+Nothing here re-types the oracle's loop. The references are of other kinds:
+boolean adjacency-matrix powers, unit-weight Bellman-Ford, closed-form distance
+formulas, and values printed in the paper (``tests/golden/``).
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+
+import graphgen
+import oracle
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def load_golden(name: str):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+# ---------------------------------------------------------------------------
+# Brute-force references
+# ---------------------------------------------------------------------------
+
+def all_graph_adjacency(n: int) -> np.ndarray:
+    """Adjacency matrices of every labelled simple undirected graph on n vertices."""
+    iu, ju = np.triu_indices(n, 1)
+    k = len(iu)
+    masks = np.arange(1 << k, dtype=np.int64)
+    bits = ((masks[:, None] >> np.arange(k)) & 1).astype(bool)
+    adj = np.zeros((1 << k, n, n), dtype=bool)
+    adj[:, iu, ju] = bits
+    adj[:, ju, iu] = bits
+    return adj
+
+
+def matrix_power_levels(adj: np.ndarray) -> np.ndarray:
+    """dist[g, r, v] = least k with (A^k)[r, v] > 0, else -1 (boolean matrix powers)."""
+    g, n, _ = adj.shape
+    a = adj.astype(np.int64)
+    dist = np.full((g, n, n), -1, dtype=np.int64)
+    reach = np.broadcast_to(np.eye(n, dtype=np.int64), (g, n, n)).copy()  # A^0
+    for k in range(n):
+        newly = (reach > 0) & (dist == -1)
+        dist[newly] = k
+        reach = np.minimum(reach @ a, 1)
+    return dist
+
+
+def bellman_ford_levels(n: int, src, dst, root: int) -> np.ndarray:
+    """Unit-weight Bellman-Ford over an arc list: relax every arc n-1 times."""
+    INF = 1 << 40
+    d = [INF] * n
+    d[root] = 0
+    for _ in range(max(n - 1, 1)):
+        changed = False
+        for a, b in zip(src, dst):
+            if d[a] + 1 < d[b]:
+                d[b] = d[a] + 1
+                changed = True
+        if not changed:
+            break
+    return np.array([x if x < INF else -1 for x in d], dtype=np.int64)
+
+
+def union_find_component(n: int, offsets, cols, root: int) -> np.ndarray:
+    """Boolean mask of root's component (undirected reading) by union-find."""
+    parent = np.arange(n)
+
+    def find(x):
+        while parent[x] != x:
+            parent[x] = parent[parent[x]]
+            x = parent[x]
+        return x
+
+    deg = np.diff(offsets)
+    src = np.repeat(np.arange(n), deg)
+    for a, b in zip(src.tolist(), np.asarray(cols).tolist()):
+        ra, rb = find(a), find(b)
+        if ra != rb:
+            parent[ra] = rb
+    r = find(root)
+    return np.array([find(v) == r for v in range(n)])
+
+
+def check_parents_python(n, offsets, cols, root, levels, parents) -> bool:
+    """Independent (pure-Python) statement of V2-V4 for small graphs."""
+    if levels[root] != 0 or parents[root] != root:
+        return False
+    for v in range(n):
+        if (levels[v] == -1) != (parents[v] == -1):
+            return False
+        if v == root or levels[v] == -1:
+            continue
+        u = int(parents[v])
+        if not (0 <= u < n) or levels[u] != levels[v] - 1:
+            return False
+        if v not in set(cols[offsets[u]:offsets[u + 1]].tolist()):
+            return False
+    return True
+
+
+# ---------------------------------------------------------------------------
+# Pin sets (each returns a list of failure strings; empty = pinned)
+# ---------------------------------------------------------------------------
+
+def pin_exhaustive(lib, n: int) -> list[str]:
+    """Every labelled simple graph on n vertices, every root, vs matrix powers."""
+    adj = all_graph_adjacency(n)
+    dist = matrix_power_levels(adj)
+    fails = []
+    for gi in range(adj.shape[0]):
+        rows, cols = np.nonzero(adj[gi])
+        offsets = np.zeros(n + 1, dtype=np.int64)
+        np.cumsum(np.bincount(rows, minlength=n), out=offsets[1:])
+        cols = cols.astype(np.int32)
+        for r in range(n):
+            lv, pa, _ = oracle.bfs(offsets, cols, r, lib=lib)
+            if not np.array_equal(lv, dist[gi, r]):
+                fails.append(f"n={n} graph={gi} root={r}: levels {lv.tolist()} != {dist[gi, r].tolist()}")
+            elif not check_parents_python(n, offsets, cols, r, lv, pa):
+                fails.append(f"n={n} graph={gi} root={r}: invalid parents {pa.tolist()}")
+            if len(fails) > 5:
+                return fails
+    return fails
+
+
+def closed_form_cases():
+    """(graph, root, expected levels, expected unique parents or None)."""
+    cases = []
+    n = 1000
+    v = np.arange(n)
+    for r in (0, 377, n - 1):
+        exp_par = np.where(v < r, v + 1, v - 1)
+        exp_par[r] = r
+        cases.append((graphgen.path(n), r, np.abs(v - r), exp_par))
+    for cn in (999, 1000):
+        r = 17
+        d = np.abs(v[:cn] - r)
+        cases.append((graphgen.cycle(cn), r, np.minimum(d, cn - d), None))
+    cases.append((graphgen.star(500), 0, np.r_[0, np.ones(499, dtype=np.int64)],
+                  np.zeros(500, dtype=np.int64)))
+    lv = np.full(500, 2)
+    lv[7], lv[0] = 0, 1
+    par = np.zeros(500, dtype=np.int64)
+    par[7], par[0] = 7, 7
+    cases.append((graphgen.star(500), 7, lv, par))
+    lv = np.ones(60, dtype=np.int64)
+    lv[11] = 0
+    cases.append((graphgen.complete(60), 11, lv, np.full(60, 11)))
+    R, C = 37, 53
+    rr, cc = np.divmod(np.arange(R * C), C)
+    root = 20 * C + 9
+    cases.append((graphgen.grid(R, C), root, np.abs(rr - 20) + np.abs(cc - 9), None))
+    nb = 4095
+    vb = np.arange(nb)
+    par = (vb - 1) // 2
+    par[0] = 0
+    cases.append((graphgen.binary_tree(nb), 0, np.floor(np.log2(vb + 1)).astype(np.int64), par))
+    g2 = graphgen.disjoint(graphgen.path(10), graphgen.complete(5))
+    lv = np.r_[np.arange(10), np.full(5, -1)]
+    cases.append((g2, 0, lv, np.r_[0, np.arange(9), np.full(5, -1)]))
+    g3 = graphgen.disjoint(graphgen.empty(1), graphgen.star(6))
+    cases.append((g3, 0, np.r_[0, np.full(6, -1)], np.r_[0, np.full(6, -1)]))
+    return cases
+
+
+def pin_closed_forms(lib) -> list[str]:
+    fails = []
+    for g, r, exp_lv, exp_par in closed_form_cases():
+        lv, pa, st = oracle.bfs(g.offsets, g.cols, r, lib=lib)
+        if not np.array_equal(lv, exp_lv):
+            bad = np.nonzero(lv != exp_lv)[0][:5]
+            fails.append(f"{g.name} root {r}: levels differ at {bad.tolist()}")
+            continue
+        if exp_par is not None and not np.array_equal(pa, exp_par):
+            fails.append(f"{g.name} root {r}: parents differ")
+        reached = int((exp_lv >= 0).sum())
+        if st["reached"] != reached or st["levels"] != int(exp_lv.max()) + 1:
+            fails.append(f"{g.name} root {r}: stats {st}")
+        if st["arcs"] != int(g.degrees()[exp_lv >= 0].sum()):
+            fails.append(f"{g.name} root {r}: arc count {st['arcs']}")
+    return fails
+
+
+def pin_paper_examples(lib) -> list[str]:
+    fails = []
+    ex = load_golden("paper_examples.json")
+    race = ex["benign_race"]
+    g = graphgen.from_edges(race["n"], *zip(*race["edges"]))
+    lv, pa, _ = oracle.bfs(g.offsets, g.cols, race["root"], lib=lib)
+    for v, lev in race["levels"].items():
+        if lv[int(v)] != lev:
+            fails.append(f"benign race: level[{v}]={lv[int(v)]} expected {lev}")
+    if int(pa[race["vertex"]]) not in race["valid_parents"]:
+        fails.append(f"benign race: parent {pa[race['vertex']]} not in {race['valid_parents']}")
+    word = ex["bit_race_word"]
+    g = graphgen.from_edges(word["n"], [word["root"]] * len(word["children"]), word["children"])
+    lv, pa, _ = oracle.bfs(g.offsets, g.cols, word["root"], lib=lib)
+    if not all(lv[c] == 1 and pa[c] == word["root"] for c in word["children"]):
+        fails.append("bit-race word: a child of the root was lost")
+    return fails
+
+
+def pin_bellman_ford(lib, n, src, dst, root) -> list[str]:
+    g = graphgen.from_edges(n, src, dst, symmetric=False, dedupe=False, drop_self_loops=False,
+                            sort_rows=False)
+    lv, pa, _ = oracle.bfs(g.offsets, g.cols, root, lib=lib)
+    ref = bellman_ford_levels(n, src, dst, root)
+    if not np.array_equal(lv, ref):
+        return [f"bellman-ford mismatch n={n} root={root}"]
+    if not check_parents_python(n, g.offsets, g.cols, root, lv, pa):
+        return [f"invalid parents n={n} root={root}"]
+    return []
+
+
+def pin_random_digraphs(lib, count: int = 60, seed: int = 11) -> list[str]:
+    rng = np.random.default_rng(seed)
+    fails = []
+    for _ in range(count):
+        n = int(rng.integers(1, 48))
+        m = int(rng.integers(0, 4 * n))
+        src = rng.integers(0, n, m)
+        dst = rng.integers(0, n, m)
+        fails += pin_bellman_ford(lib, n, src.tolist(), dst.tolist(), int(rng.integers(0, n)))
+    return fails

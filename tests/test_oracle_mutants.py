@@ -1,0 +1,58 @@
+"""The oracle's pins catch plausible mistakes.
+
+Each case compiles a copy of ``oracle/bfs_oracle.c`` with one textual mistake
+planted (a dropped term, a wrong index, LIFO instead of FIFO, an off-by-one
+bound, a transposed operand) and checks that at least one pin fails. The
+mistakes are planted in copies of the oracle on the CPU only.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _run_pins(so_path):
+    """Run the pin sets on one oracle build in a child process (a crash counts as caught)."""
+    return subprocess.run([sys.executable, "-m", "tests.run_pins", so_path], cwd=ROOT,
+                          capture_output=True, text=True, timeout=300)
+
+MUTANTS = {
+    "level_plus_two": ("levels[v] = levels[u] + 1;", "levels[v] = levels[u] + 2;"),
+    "level_from_parent_missing": ("levels[v] = levels[u] + 1;", "levels[v] = 1;"),
+    "parent_self": ("parents[v] = u;", "parents[v] = v;"),
+    "parent_dropped": ("parents[v] = u;", ";"),
+    "lifo_queue": ("int32_t u = queue[head++];", "int32_t u = queue[--tail]; head += 0;"),
+    "last_neighbour_dropped": ("for (int64_t j = begin; j < end; ++j)", "for (int64_t j = begin; j + 1 < end; ++j)"),
+    "first_neighbour_dropped": ("for (int64_t j = begin; j < end; ++j)", "for (int64_t j = begin + 1; j < end; ++j)"),
+    "visited_test_inverted": ("if (levels[v] == -1) {", "if (levels[v] != 0) {"),
+    "root_level_one": ("levels[root] = 0;", "levels[root] = 1;"),
+    "root_parent_missing": ("parents[root] = (int32_t)root;", "parents[root] = -1;"),
+    "row_end_wrong": ("end = offsets[u + 1];", "end = offsets[u] + 1;"),
+    "operand_transposed": ("int32_t v = cols[j];", "int32_t v = (int32_t)(j % n);"),
+    "init_zero": ("levels[v] = -1;\n        parents[v] = -1;", "levels[v] = 0;\n        parents[v] = -1;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(oracle._SRC).read()
+    assert old in src, f"mutation anchor for {name} not found"
+    mutated = tmp_path / f"oracle_{name}.c"
+    mutated.write_text(src.replace(old, new, 1))
+    so = oracle.build(force=True, src=str(mutated), out=str(tmp_path / f"lib_{name}.so"))
+    r = _run_pins(so)
+    assert r.returncode != 0, f"mutant {name} passed every pin:\n{r.stdout}"
+
+
+def test_unmutated_copy_passes(tmp_path):
+    src = open(oracle._SRC).read()
+    p = tmp_path / "oracle_copy.c"
+    p.write_text(src)
+    r = _run_pins(oracle.build(force=True, src=str(p), out=str(tmp_path / "lib.so")))
+    assert r.returncode == 0, r.stdout + r.stderr

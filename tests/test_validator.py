@@ -1,0 +1,61 @@
+"""The validator accepts every valid BFS tree and rejects mutated outputs (V1-V4)."""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from tests import pins
+
+
+@pytest.fixture(scope="module")
+def case():
+    g = graphgen.rmat(10, seed=1)
+    r = int(graphgen.pick_roots(g, 1, seed=2)[0])
+    lv, pa, _ = oracle.bfs(g.offsets, g.cols, r)
+    return g, r, lv, pa
+
+
+def test_accepts_oracle(case):
+    g, r, lv, pa = case
+    assert oracle.validate(g.offsets, g.cols, r, lv, lv, pa) == (0, -1)
+
+
+def test_accepts_other_valid_parent():
+    race = pins.load_golden("paper_examples.json")["benign_race"]
+    g = graphgen.from_edges(race["n"], *zip(*race["edges"]))
+    lv, pa, _ = oracle.bfs(g.offsets, g.cols, race["root"])
+    for p in race["valid_parents"]:
+        alt = pa.copy()
+        alt[race["vertex"]] = p
+        assert oracle.validate(g.offsets, g.cols, race["root"], lv, lv, alt)[0] == 0
+
+
+def test_rejects_mutations(case):
+    g, r, lv, pa = case
+    reached = np.nonzero((lv > 0))[0]
+    v = int(reached[len(reached) // 2])
+    # V1: shifted level
+    m = lv.copy(); m[v] += 1
+    assert oracle.validate(g.offsets, g.cols, r, lv, m, pa)[0] == 1
+    # V1: dropped reached vertex
+    m = lv.copy(); m[v] = -1
+    p = pa.copy(); p[v] = -1
+    assert oracle.validate(g.offsets, g.cols, r, lv, m, p)[0] == 1
+    # V2: root not its own parent
+    p = pa.copy(); p[r] = int(g.cols[g.offsets[r]])
+    assert oracle.validate(g.offsets, g.cols, r, lv, lv, p)[0] == 2
+    # V3: reached vertex without parent
+    p = pa.copy(); p[v] = -1
+    assert oracle.validate(g.offsets, g.cols, r, lv, lv, p)[0] == 3
+    # V4: parent at the same level / not adjacent / out of range
+    same = np.nonzero(lv == lv[v])[0]
+    p = pa.copy(); p[v] = int(same[same != v][0])
+    assert oracle.validate(g.offsets, g.cols, r, lv, lv, p)[0] == 4
+    up = np.nonzero(lv == lv[v] - 1)[0]
+    row = set(g.cols[g.offsets[v]:g.offsets[v + 1]].tolist())
+    nonadj = [u for u in up.tolist() if u not in row]
+    if nonadj:
+        p = pa.copy(); p[v] = nonadj[0]
+        assert oracle.validate(g.offsets, g.cols, r, lv, lv, p) == (4, v)
+    p = pa.copy(); p[v] = g.n + 3
+    assert oracle.validate(g.offsets, g.cols, r, lv, lv, p)[0] == 4

@@ -1,0 +1,221 @@
+/*
+ * bfs.h — C ABI of libbfs.so: level-synchronous top-down breadth-first search
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * The problem statement follows the paper (Paredes, Riley, Lujan, "Breadth
+ * First Search Vectorization on the Intel Xeon Phi", arXiv 1604.02844):
+ * section 3 — given a graph G and a source vertex s, explore every edge that
+ * can be reached from s and output a BFS spanning tree as a predecessor list;
+ * layers L_k hold the vertices at distance k (distance = number of edges on a
+ * shortest path) and are processed in order; section 3.1, Algorithm 1 — every
+ * vertex starts with no predecessor, the source is its own predecessor, and a
+ * neighbour that is not yet visited is marked visited, put in the next layer
+ * and given the expanding vertex as predecessor; section 3.3.1 — the graph is
+ * stored as CSR and the visited / input / output sets are bitmaps of 32-bit
+ * words (vertex v in word v/32, bit v%32).
+ *
+ * Output conventions (shared by every call that returns a BFS result):
+ *   levels[v]  = hop distance from the root, or -1 when v is unreached
+ *                (unique, so it is reproducible exactly);
+ *   parents[v] = a vertex u with levels[u] == levels[v]-1 and an arc u->v;
+ *                parents[root] = root; -1 when v is unreached. When several
+ *                parents are valid any one may be returned (section 3.2: the
+ *                parent race is benign and different correct BFS trees can
+ *                result), so parents may differ between runs.
+ *
+ * General rules:
+ *   - Every function returns an int status: BFS_OK (0), BFS_PENDING (1, poll
+ *     only) or a negative BFS_E_* error. No C++ exception crosses this ABI.
+ *   - Vertex ids are int32 (n <= 2^31-1); arc positions are int64.
+ *   - Pointers are host pointers unless a flag says otherwise. "Device
+ *     pointer" means memory from hipMalloc (or a torch CUDA tensor) on the
+ *     device the library runs on.
+ *   - A `stream` argument is a hipStream_t passed as void*; NULL means the
+ *     default (null) stream.
+ */
+#ifndef BFS_H
+#define BFS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+#define BFS_OK 0
+#define BFS_PENDING 1              /* bfs_server_poll: request not finished yet */
+#define BFS_E_INVALID_ARG (-1)     /* NULL pointer, bad size, bad flag combination */
+#define BFS_E_INVALID_GRAPH (-2)   /* n<1, n>2^31-1, offsets[0]!=0, decreasing offsets,
+                                      offsets[n]!=nnz, or a column outside [0,n) */
+#define BFS_E_ROOT_RANGE (-3)      /* a root outside [0,n) */
+#define BFS_E_NO_MEMORY (-4)       /* device or host allocation failed, or over budget */
+#define BFS_E_DEVICE (-5)          /* a HIP runtime error */
+#define BFS_E_UNKNOWN_TICKET (-6)  /* ticket never issued or already consumed */
+#define BFS_E_BUSY (-7)            /* object still in use (e.g. graph held by a server) */
+#define BFS_E_SHUTDOWN (-8)        /* server is shutting down */
+#define BFS_E_INTERNAL (-9)        /* an unexpected internal failure */
+
+/* ---- flags --------------------------------------------------------------- */
+/* bfs_graph_load_csr */
+#define BFS_LOAD_DEVICE_PTRS 0x1u   /* offsets/cols are device pointers, borrowed (not
+                                       copied): they must outlive the graph */
+#define BFS_LOAD_SKIP_VALIDATE 0x2u /* trust the CSR; skip the O(n+nnz) checks */
+#define BFS_LOAD_OFFSETS_I32 0x4u   /* offsets points at int32_t[n+1] instead of int64_t[n+1];
+                                       the graph keeps 4-byte offsets on the device */
+/* bfs_run / bfs_run_batch */
+#define BFS_OUT_HOST 0x1u           /* levels/parents are host pointers (results are copied
+                                       back before return; implies synchronous) */
+#define BFS_ASYNC 0x2u              /* enqueue on `stream` and return; stats must be NULL */
+
+typedef struct bfs_graph bfs_graph;
+typedef struct bfs_server bfs_server;
+
+/* Totals of one run (for a batch: summed over roots, num_levels = max). */
+typedef struct {
+    int32_t num_levels;      /* non-empty layers = max level + 1 */
+    int32_t num_roots;       /* 1 for bfs_run */
+    int64_t reached;         /* vertices with level >= 0 */
+    int64_t arcs_scanned;    /* sum of out-degrees of reached vertices */
+    int64_t edges_traversed; /* arcs_scanned / 2: undirected edges of the root's
+                                component on a symmetric graph (the TEPS numerator) */
+    double device_ms;        /* device time of the run (HIP events on `stream`) */
+} bfs_run_stats;
+
+/* Kernel tunables. Zero fields mean "library default". See bfs_autotune. */
+typedef struct {
+    int32_t small_max_degree;   /* T1: rows with d <= T1 are packed, several per wavefront */
+    int32_t wave_max_degree;    /* T2: T1 < d <= T2 gets one wavefront; rows with d > T2 are
+                                   cut into chunks of chunk_arcs arcs, one workgroup each */
+    int32_t chunk_arcs;         /* arcs per workgroup chunk of a row above T2 */
+    int32_t blocks_per_cu;      /* workgroups per compute unit of the expansion grid */
+    int32_t block_size;         /* threads per workgroup: 256 or 512 */
+    int32_t batch_width;        /* bfs_run_batch: roots per bit-sliced pass (1..64) */
+    int32_t update_mode;        /* bitmap update: 1 = plain read-modify-write followed by the
+                                   restoration pass (the paper's atomic-free scheme, section
+                                   3.3.2), 2 = atomicOr claim; 0 = library default */
+    int32_t reserved;
+} bfs_tunables;
+
+/* ---- graph residency ------------------------------------------------------ */
+
+/*
+ * Make a CSR graph resident on the current HIP device.
+ *   n        number of vertices, 1 <= n <= 2^31-1.
+ *   nnz      number of arcs (directed CSR entries), >= 0.
+ *   offsets  int64_t[n+1] (int32_t[n+1] with BFS_LOAD_OFFSETS_I32): row v is
+ *            cols[offsets[v] .. offsets[v+1]). offsets[0]==0, offsets[n]==nnz,
+ *            non-decreasing.
+ *   cols     int32_t[nnz] out-neighbours, each in [0,n). Rows need not be sorted;
+ *            self-loops and duplicate arcs are allowed and do not change levels.
+ * The CSR is read as out-adjacency (any directed graph is accepted; a symmetric
+ * CSR gives undirected BFS). Host inputs are copied and the library owns the
+ * device copy; with BFS_LOAD_DEVICE_PTRS the caller's device arrays are used in
+ * place. Returns BFS_E_INVALID_GRAPH when validation fails (nothing allocated).
+ */
+int bfs_graph_load_csr(int64_t n, int64_t nnz, const void* offsets, const int32_t* cols,
+                       uint32_t flags, bfs_graph** out);
+
+/* Release a graph and every buffer the library allocated for it.
+ * BFS_E_BUSY if a server still holds it. NULL is accepted (no-op). */
+int bfs_graph_free(bfs_graph* g);
+
+/* Size of a resident graph; any output pointer may be NULL. device_bytes counts
+ * library-owned device memory (CSR copy, hub table, cached workspaces). */
+int bfs_graph_info(const bfs_graph* g, int64_t* n, int64_t* nnz, int64_t* device_bytes);
+
+/* Read or replace the tunables used by later runs on this graph. */
+int bfs_graph_get_tunables(const bfs_graph* g, bfs_tunables* t);
+int bfs_graph_set_tunables(bfs_graph* g, const bfs_tunables* t);
+
+/* ---- single-root BFS -------------------------------------------------------- */
+
+/*
+ * One top-down BFS from `root` (section 3.1, Algorithm 1; parallel form of
+ * section 3.2, Algorithm 2, with the bitmap data structures of section 3.3.1).
+ *   levels, parents  int32_t[n] each, written in full (caller-allocated; device
+ *                    pointers unless BFS_OUT_HOST).
+ *   stream           hipStream_t or NULL.
+ *   flags            BFS_OUT_HOST, BFS_ASYNC (not both).
+ *   st               nullable; filled on return (must be NULL with BFS_ASYNC).
+ * Errors: BFS_E_ROOT_RANGE, BFS_E_INVALID_ARG, BFS_E_DEVICE, BFS_E_NO_MEMORY.
+ * Reentrant for distinct streams and outputs on the same graph.
+ */
+int bfs_run(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents, void* stream,
+            uint32_t flags, bfs_run_stats* st);
+
+/* ---- batched multi-source BFS --------------------------------------------------- */
+
+/*
+ * Independent BFS from each of num_roots roots, computed together: one
+ * persistent launch per group of up to 64 roots, every vertex carrying a 64-bit
+ * visited / frontier mask (bit i = root i of the group). Results are exactly
+ * those of num_roots separate bfs_run calls (levels identical, parents valid).
+ *   roots    host int32_t[num_roots]; duplicates allowed.
+ *   levels   int32_t[num_roots * n], row-major: root i's levels at [i*n, (i+1)*n).
+ *   parents  int32_t[num_roots * n], same layout.
+ * Flags and stats as for bfs_run (stats are summed over roots).
+ */
+int bfs_run_batch(bfs_graph* g, const int32_t* roots, int32_t num_roots, int32_t* levels,
+                  int32_t* parents, void* stream, uint32_t flags, bfs_run_stats* st);
+
+/* ---- autotuner ------------------------------------------------------------- */
+
+/*
+ * Time candidate tunables on this graph with the given sample roots and keep
+ * the fastest (also applied to the graph). mode 0 tunes bfs_run, mode 1 tunes
+ * bfs_run_batch. Candidate results are checked against the default
+ * configuration's levels; a candidate that differs is rejected. best may be NULL.
+ */
+int bfs_autotune(bfs_graph* g, const int32_t* roots, int32_t num_roots, int32_t mode,
+                 bfs_tunables* best);
+
+/* ---- serving --------------------------------------------------------------- */
+
+typedef struct {
+    int64_t mem_budget_bytes;       /* device bytes for instances and results; 0 = 50% of free */
+    int32_t max_slots;              /* roots per multi-source instance (1..64); 0 = 64 */
+    int32_t num_streams;            /* HIP streams shared by instances; 0 = 4 */
+    int32_t max_instances_per_graph;/* concurrent instances of one graph; 0 = 2 */
+    int32_t flags;                  /* reserved, must be 0 */
+} bfs_server_config;
+
+typedef struct {
+    int32_t num_levels;
+    int32_t graph_id;
+    int64_t reached;
+    int64_t arcs_scanned;
+    int64_t edges_traversed;
+    double queue_ms;    /* submit -> admitted into an instance slot */
+    double latency_ms;  /* submit -> result complete on the device */
+} bfs_request_stats;
+
+/* Start a server (a scheduler thread plus HIP streams). cfg may be NULL. */
+int bfs_server_create(const bfs_server_config* cfg, bfs_server** out);
+
+/* Register a resident graph; the server borrows it until destroyed. */
+int bfs_server_add_graph(bfs_server* s, bfs_graph* g, int32_t* graph_id);
+
+/* Queue one BFS request (thread-safe). A ticket is returned for polling. */
+int bfs_server_submit(bfs_server* s, int32_t graph_id, int32_t root, uint64_t* ticket);
+
+/*
+ * Poll a ticket (thread-safe). BFS_PENDING while queued or running; BFS_OK once
+ * done: levels/parents (int32_t[n] each; host or device pointers, copied with
+ * hipMemcpyDefault; either may be NULL to skip) receive the result, st
+ * (nullable) the request's stats, and the ticket is consumed.
+ */
+int bfs_server_poll(bfs_server* s, uint64_t ticket, int32_t* levels, int32_t* parents,
+                    bfs_request_stats* st);
+
+/* Stop the scheduler, drop pending requests and free server memory. */
+int bfs_server_destroy(bfs_server* s);
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char* bfs_status_str(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BFS_H */

@@ -9,6 +9,8 @@ with gcc) and shares no code with the GPU library.
                 FIFO-first ``parents``.
 * ``validate``  V1-V4 check of a candidate ``(levels, parents)`` against the
                 oracle's levels (the parent choice is free; section 3.2).
+* ``certify``   V2-V5 check of a candidate on its own (no oracle levels): exact
+                when levels are hop distances and parents form a BFS tree.
 * ``bfs_many``  the same serial BFS from several roots, one root per host
                 thread, used only to time the CPU baseline.
 """
@@ -28,7 +30,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 CHECK_NAMES = {0: "ok", 1: "V1 levels differ", 2: "V2 root", 3: "V3 reached set / parent -1",
-               4: "V4 parent not adjacent one level up"}
+               4: "V4 parent not adjacent one level up", 5: "V5 arc skips a level or leaves the reached set"}
 
 
 def build(force: bool = False, src: str = _SRC, out: str = _LIB_PATH) -> str:
@@ -47,6 +49,8 @@ def load_library(path: str):
     lib.oracle_bfs.argtypes = [i64, vp, vp, i64, vp, vp, vp]
     lib.oracle_validate.restype = ctypes.c_int
     lib.oracle_validate.argtypes = [i64, vp, vp, i64, vp, vp, vp, ctypes.c_int, vp]
+    lib.oracle_certify.restype = ctypes.c_int
+    lib.oracle_certify.argtypes = [i64, vp, vp, i64, vp, vp, ctypes.c_int, vp]
     return lib
 
 
@@ -99,6 +103,24 @@ def validate(offsets, cols, root: int, ref_levels, levels, parents, rows_sorted:
                              lv.ctypes.data, pa.ctypes.data, int(bool(rows_sorted)), bad.ctypes.data)
     if rc < 0:
         raise ValueError(f"oracle_validate argument error ({rc})")
+    return rc, int(bad[0])
+
+
+def certify(offsets, cols, root: int, levels, parents, rows_sorted: bool = True, lib=None):
+    """V2-V5 without oracle levels: ``(code, bad_vertex)``, code 0 = levels are the
+    hop distances and parents a BFS tree."""
+    lib = lib or _load()
+    off = _as64(offsets)
+    col = _as32(cols)
+    n = len(off) - 1
+    lv, pa = _as32(levels), _as32(parents)
+    if not (len(lv) == len(pa) == n):
+        raise ValueError("length mismatch")
+    bad = np.full(1, -1, dtype=np.int64)
+    rc = lib.oracle_certify(n, off.ctypes.data, col.ctypes.data, int(root), lv.ctypes.data, pa.ctypes.data,
+                            int(bool(rows_sorted)), bad.ctypes.data)
+    if rc < 0:
+        raise ValueError(f"oracle_certify argument error ({rc})")
     return rc, int(bad[0])
 
 

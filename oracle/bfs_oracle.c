@@ -31,6 +31,15 @@
  *                    other reached vertex has a parent in range, one level up,
  *                    joined to it by an arc parent -> vertex.
  *
+ *   oracle_certify   The same verdict without running a BFS, for outputs too
+ *                    large to recompute one by one: V2-V4 plus V5, every arc
+ *                    u -> v leaving a reached u reaches v with
+ *                    levels[v] <= levels[u] + 1. The parent chain of V4 bounds
+ *                    levels[v] from below by the hop distance (it is a walk of
+ *                    levels[v] arcs from the root) and V5 applied along a
+ *                    shortest path bounds it from above, so V2-V5 hold exactly
+ *                    when levels[] is the hop distance and parents[] a BFS tree.
+ *
  * Pins: tests/test_oracle_*.py check this file against brute force on every
  * labelled graph with n <= 6, unit-weight Bellman-Ford on random digraphs,
  * closed forms (path, cycle, star, complete graph, grid, binary tree, disjoint
@@ -103,23 +112,10 @@ static int has_arc(const int64_t* offsets, const int32_t* cols, int64_t u, int32
     return lo < offsets[u + 1] && cols[lo] == v;
 }
 
-/*
- * Returns 0 when the candidate passes V1-V4, otherwise the number (1..4) of the
- * first failing check; *bad_vertex (nullable) receives the offending vertex.
- * Negative returns are argument errors.
- */
-int oracle_validate(int64_t n, const int64_t* offsets, const int32_t* cols, int64_t root,
-                    const int32_t* ref_levels, const int32_t* levels, const int32_t* parents,
-                    int rows_sorted, int64_t* bad_vertex) {
-    if (n < 1 || !offsets || !ref_levels || !levels || !parents) return ORACLE_E_ARG;
-    if (root < 0 || root >= n) return ORACLE_E_ROOT;
-    if (bad_vertex) *bad_vertex = -1;
-    for (int64_t v = 0; v < n; ++v) { /* V1 */
-        if (levels[v] != ref_levels[v]) {
-            if (bad_vertex) *bad_vertex = v;
-            return 1;
-        }
-    }
+/* V2-V4 of a candidate against its own levels (shared by both checks). */
+static int check_tree(int64_t n, const int64_t* offsets, const int32_t* cols, int64_t root,
+                      const int32_t* levels, const int32_t* parents, int rows_sorted,
+                      int64_t* bad_vertex) {
     if (levels[root] != 0 || parents[root] != root) { /* V2 */
         if (bad_vertex) *bad_vertex = root;
         return 2;
@@ -137,6 +133,56 @@ int oracle_validate(int64_t n, const int64_t* offsets, const int32_t* cols, int6
             !has_arc(offsets, cols, u, (int32_t)v, rows_sorted)) {
             if (bad_vertex) *bad_vertex = v;
             return 4;
+        }
+    }
+    return 0;
+}
+
+/*
+ * Returns 0 when the candidate passes V1-V4, otherwise the number (1..4) of the
+ * first failing check; *bad_vertex (nullable) receives the offending vertex.
+ * Negative returns are argument errors.
+ */
+int oracle_validate(int64_t n, const int64_t* offsets, const int32_t* cols, int64_t root,
+                    const int32_t* ref_levels, const int32_t* levels, const int32_t* parents,
+                    int rows_sorted, int64_t* bad_vertex) {
+    if (n < 1 || !offsets || !ref_levels || !levels || !parents) return ORACLE_E_ARG;
+    if (root < 0 || root >= n) return ORACLE_E_ROOT;
+    if (bad_vertex) *bad_vertex = -1;
+    for (int64_t v = 0; v < n; ++v) { /* V1 */
+        if (levels[v] != ref_levels[v]) {
+            if (bad_vertex) *bad_vertex = v;
+            return 1;
+        }
+    }
+    return check_tree(n, offsets, cols, root, levels, parents, rows_sorted, bad_vertex);
+}
+
+/*
+ * V2-V5 without oracle levels (see the header). Returns 0 or the failing check
+ * number (2..5); negative on argument errors.
+ */
+int oracle_certify(int64_t n, const int64_t* offsets, const int32_t* cols, int64_t root,
+                   const int32_t* levels, const int32_t* parents, int rows_sorted, int64_t* bad_vertex) {
+    if (n < 1 || !offsets || !levels || !parents) return ORACLE_E_ARG;
+    if (root < 0 || root >= n) return ORACLE_E_ROOT;
+    if (bad_vertex) *bad_vertex = -1;
+    for (int64_t v = 0; v < n; ++v) {
+        if (levels[v] < -1 || levels[v] >= n) {
+            if (bad_vertex) *bad_vertex = v;
+            return 3;
+        }
+    }
+    int rc = check_tree(n, offsets, cols, root, levels, parents, rows_sorted, bad_vertex);
+    if (rc) return rc;
+    for (int64_t u = 0; u < n; ++u) { /* V5 */
+        if (levels[u] == -1) continue;
+        for (int64_t j = offsets[u]; j < offsets[u + 1]; ++j) {
+            int32_t v = cols[j];
+            if (levels[v] == -1 || levels[v] > levels[u] + 1) {
+                if (bad_vertex) *bad_vertex = v;
+                return 5;
+            }
         }
     }
     return 0;

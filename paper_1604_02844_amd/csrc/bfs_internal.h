@@ -1,0 +1,167 @@
+// Internal declarations of libbfs: graph residency, workspaces, launch helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/bfs.h"
+
+namespace bfs {
+
+// An error that maps to one ABI status code.
+struct Error : std::runtime_error {
+    int status;
+    Error(int s, const std::string& msg) : std::runtime_error(msg), status(s) {}
+};
+
+[[noreturn]] void fail(int status, const std::string& msg);
+void hip_check(hipError_t e, const char* what);
+#define BFS_HIP(call) ::bfs::hip_check((call), #call)
+
+constexpr int kStripes = 64;       // striped counters: one 128-byte line each
+constexpr int kStripeStride = 16;  // u64 per stripe (128 bytes)
+
+// Device-side control block of one run. Per-level counters are striped over
+// separate cache lines (device-scope atomics on one address serialise) and
+// double-buffered by level parity.
+struct Ctrl {
+    unsigned long long newcnt[2][kStripes * kStripeStride];  // vertices found per level
+    unsigned long long reached;    // totals, written by the final stats kernel
+    unsigned long long arcs;
+    unsigned long long alive[3];   // multi-source: OR of new root bits per level (ring)
+    unsigned long long newcnt_ms[3];
+    int done;                      // set by the first level that finds an empty frontier
+    int num_levels;
+    int status;
+    int pad;
+};
+
+// Scratch of one single-root run.
+struct Workspace {
+    int device = 0;
+    int64_t words = 0;              // 32-bit words per bitmap (padded to 64)
+    uint32_t* vis = nullptr;        // visited bits, updated during a level
+    uint32_t* vis_prev = nullptr;   // exact visited bits at the start of the level
+    uint32_t* fr = nullptr;         // exact frontier bits of the current level
+    Ctrl* ctrl = nullptr;
+    unsigned long long* slots = nullptr;  // per-block partial sums (arcs | reached)
+    int64_t nslots = 0;
+    Ctrl* host_ctrl = nullptr;      // pinned mirror for stats
+    int32_t* out_levels = nullptr;  // staging for BFS_OUT_HOST
+    int32_t* out_parents = nullptr;
+    hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev_free = nullptr;
+    bool used = false;
+    int64_t bytes = 0;
+};
+
+// Device control block of a multi-source instance (64 root slots).
+struct MsCtrl {
+    // Striped per-level statistics, double-buffered by level parity:
+    // discoveries, arcs of the next frontier's rows, OR of discovered slot bits.
+    unsigned long long disc[2][kStripes * kStripeStride];
+    unsigned long long arcs[2][kStripes * kStripeStride];
+    unsigned long long alive[2][kStripes * kStripeStride];
+    unsigned long long work[kStripes * kStripeStride];  // batch: sum of deg(v) * roots holding v
+    unsigned long long slot_reached[64];  // per-slot totals (serving)
+    unsigned long long slot_arcs[64];
+    int32_t* out_lv[64];                  // per-slot output rows
+    int32_t* out_pa[64];
+    int32_t start[64];                    // level at which each slot joined
+    unsigned long long active;            // slots still running (host-managed)
+    unsigned long long sum_disc;          // summary of one parity (k_ms_summary)
+    unsigned long long sum_arcs;
+    unsigned long long sum_alive;
+    unsigned long long total_disc;        // batch totals
+    unsigned long long total_arcs;
+    int done;
+    int num_levels;
+};
+
+// Scratch of one multi-source instance: masks, frontier double buffer, control.
+struct MsWorkspace {
+    int device = 0;
+    int64_t n = 0;
+    unsigned long long* vis = nullptr;
+    unsigned long long* fr[2] = {nullptr, nullptr};
+    MsCtrl* ctrl = nullptr;
+    MsCtrl* host_ctrl = nullptr;  // pinned mirror
+    int32_t* out_levels = nullptr;  // staging for BFS_OUT_HOST ([64*n])
+    int32_t* out_parents = nullptr;
+    hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev_free = nullptr;
+    bool used = false;
+    int64_t bytes = 0;
+};
+
+}  // namespace bfs
+
+struct bfs_graph {
+    int device = 0;
+    int64_t n = 0, nnz = 0;
+    bool off32 = false;        // 4-byte offsets on the device
+    bool owns = true;          // device arrays allocated by the library
+    void* d_off = nullptr;     // int64_t[n+1] or int32_t[n+1]
+    int32_t* d_col = nullptr;  // int32_t[nnz]
+    int64_t max_degree = 0;
+    int cu_count = 0;
+
+    // Rows with degree > big_threshold are split over the whole grid: their
+    // ids, the exclusive prefix sum of their degrees, and a bitmap marking them.
+    int32_t big_threshold = 0;
+    int32_t num_big = 0;
+    int64_t big_arcs = 0;
+    int32_t* d_big = nullptr;
+    int64_t* d_big_prefix = nullptr;
+    uint32_t* d_bigmap = nullptr;
+
+    bfs_tunables tun{};
+    std::mutex mu;
+    std::vector<bfs::Workspace*> ws_free;
+    std::vector<bfs::Workspace*> ws_all;
+    std::vector<bfs::MsWorkspace*> ms_free;
+    std::vector<bfs::MsWorkspace*> ms_all;
+    std::atomic<int> server_refs{0};
+    int64_t device_bytes = 0;
+};
+
+namespace bfs {
+
+bfs_tunables default_tunables(const bfs_graph* g);
+bfs_tunables resolve_tunables(const bfs_graph* g, const bfs_tunables& t);
+void rebuild_big(bfs_graph* g, int32_t threshold);
+
+Workspace* acquire_ws(bfs_graph* g, hipStream_t s);
+void release_ws(bfs_graph* g, Workspace* w, hipStream_t s);
+MsWorkspace* acquire_ms(bfs_graph* g, hipStream_t s);
+void release_ms(bfs_graph* g, MsWorkspace* w, hipStream_t s);
+void free_workspaces(bfs_graph* g);
+
+// Launchers (the kernels live in single.hip and multi.hip).
+void launch_single(bfs_graph* g, const bfs_tunables& t, Workspace* w, int32_t root, int32_t* levels,
+                   int32_t* parents, hipStream_t s);
+void launch_single_stats(Workspace* w, hipStream_t s);
+void launch_fill_i32(int32_t* p, int64_t count, int32_t value, hipStream_t s);
+
+// Multi-source engine (multi.hip). A batch runs every level device-side with
+// chunked host checks; the server steps one level at a time.
+void ms_run_batch(bfs_graph* g, const bfs_tunables& t, MsWorkspace* w, const int32_t* roots, int32_t count,
+                  int32_t* levels, int32_t* parents, int64_t ld, hipStream_t s);
+void ms_reset(bfs_graph* g, MsWorkspace* w, hipStream_t s);
+// Seed slots (host arrays) into the frontier of instance level `level`: root
+// bits and level-0 outputs. The slot output pointers and start levels must
+// already be in w->ctrl.
+void ms_join(bfs_graph* g, MsWorkspace* w, const int32_t* slots, const int32_t* roots, int32_t count, int level,
+             hipStream_t s);
+// Expand one level of the instance; returns after the step's summary is on the
+// host (w->host_ctrl->sum_*). `level` is the instance level being expanded.
+void ms_step(bfs_graph* g, const bfs_tunables& t, MsWorkspace* w, int level, hipStream_t s, bool per_slot);
+void ms_retire(bfs_graph* g, MsWorkspace* w, unsigned long long keep, hipStream_t s);
+
+int device_cu_count(int device);
+
+}  // namespace bfs

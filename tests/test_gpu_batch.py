@@ -1,0 +1,114 @@
+"""GPU parity of batched multi-source BFS (bfs_run_batch through the C ABI):
+every root's row has the oracle's levels and a valid BFS tree."""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+import paper_1604_02844_amd as bfs
+from tests import pins
+from tests.gpu_helpers import load, torch_mod
+
+pytestmark = pytest.mark.gpu
+
+
+def run_batch(dg, roots):
+    torch = torch_mod()
+    roots = np.asarray(roots, dtype=np.int32)
+    lv = torch.empty((len(roots), dg.n), dtype=torch.int32, device="cuda")
+    pa = torch.empty((len(roots), dg.n), dtype=torch.int32, device="cuda")
+    st = bfs.bfs_run_batch(dg, roots, lv, pa)
+    return lv.cpu().numpy(), pa.cpu().numpy(), st
+
+
+def check_batch(g, dg, roots, rows_sorted=True):
+    print(f"[case] bfs_run_batch {g.name} n={g.n} roots={len(roots)}", flush=True)
+    lv, pa, st = run_batch(dg, roots)
+    reached = arcs = 0
+    for i, r in enumerate(roots):
+        ref, _, ost = oracle.bfs(g.offsets, g.cols, int(r))
+        code, bad = oracle.validate(g.offsets, g.cols, int(r), ref, lv[i], pa[i], rows_sorted=rows_sorted)
+        assert code == 0, f"{g.name} slot {i} root {r}: {oracle.CHECK_NAMES[code]} at {bad}"
+        reached += ost["reached"]
+        arcs += ost["arcs"]
+    assert st["reached"] == reached and st["arcs_scanned"] == arcs, (st, reached, arcs)
+    assert st["num_roots"] == len(roots)
+    return lv, pa, st
+
+
+def test_closed_forms_batch():
+    for g, r, exp_lv, _ in pins.closed_form_cases():
+        roots = [r, 0, g.n - 1, r]  # includes a duplicate root
+        check_batch(g, load(g), roots)
+
+
+@pytest.mark.parametrize("width", [1, 8, 31, 32, 33, 63, 64, 65, 128])
+def test_uneven_batch_widths(width):
+    g = graphgen.rmat(12, 16, seed=31)
+    roots = graphgen.pick_roots(g, width, seed=32)
+    if len(roots) < width:  # repeat roots to reach the width
+        roots = np.resize(roots, width)
+    check_batch(g, load(g), roots)
+
+
+def test_duplicate_and_isolated_roots():
+    g = graphgen.disjoint(graphgen.rmat(10, 16, seed=33), graphgen.empty(5))
+    roots = [g.n - 1, 3, 3, g.n - 2, 7]
+    check_batch(g, load(g), roots)
+
+
+@pytest.mark.parametrize("kind", ["rmat", "er"])
+def test_batch_matches_single_root(kind):
+    g = graphgen.rmat(14, 16, seed=34) if kind == "rmat" else graphgen.er(1 << 14, 16, seed=35)
+    dg = load(g)
+    roots = graphgen.pick_roots(g, 40, seed=36)
+    lv, pa, _ = check_batch(g, dg, roots)
+    torch = torch_mod()
+    one_l = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    one_p = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    for i in (0, 17, 39):
+        bfs.bfs_run(dg, int(roots[i]), one_l, one_p)
+        assert np.array_equal(one_l.cpu().numpy(), lv[i])
+
+
+@pytest.mark.parametrize("tun", [dict(small_max_degree=1, wave_max_degree=1), dict(wave_max_degree=100000),
+                                 dict(batch_width=7), dict(batch_width=64, blocks_per_cu=1)])
+def test_batch_tunables(tun):
+    g = graphgen.rmat(13, 16, seed=37)
+    dg = load(g)
+    bfs.bfs_graph_set_tunables(dg, **tun)
+    check_batch(g, dg, graphgen.pick_roots(g, 20, seed=38))
+
+
+def test_batch_int32_offsets_and_host_output():
+    g = graphgen.rmat(10, 16, seed=1)
+    dg = load(g, offsets_i32=True)
+    roots = graphgen.pick_roots(g, 16, seed=2)
+    lv = np.empty((len(roots), g.n), dtype=np.int32)
+    pa = np.empty((len(roots), g.n), dtype=np.int32)
+    bfs.bfs_run_batch(dg, roots, lv, pa)  # host buffers: BFS_OUT_HOST
+    for i, r in enumerate(roots):
+        ref, _, _ = oracle.bfs(g.offsets, g.cols, int(r))
+        assert oracle.validate(g.offsets, g.cols, int(r), ref, lv[i], pa[i])[0] == 0
+
+
+def test_batch_errors():
+    g = graphgen.path(10)
+    dg = load(g)
+    torch = torch_mod()
+    lv = torch.empty((2, 10), dtype=torch.int32, device="cuda")
+    with pytest.raises(bfs.BfsError) as e:
+        bfs.bfs_run_batch(dg, [0, 10], lv, lv)
+    assert e.value.status == bfs.BFS_E_ROOT_RANGE
+    with pytest.raises(bfs.BfsError) as e:
+        bfs.bfs_run_batch(dg, np.zeros(0, dtype=np.int32), lv, lv)
+    assert e.value.status == bfs.BFS_E_INVALID_ARG
+
+
+def test_er_batches_8_32_64():
+    """Uniform random graph (2^16 vertices, average degree 16), batches of 8, 32, 64."""
+    g = graphgen.er(1 << 16, 16, seed=39)
+    dg = load(g)
+    pool = graphgen.pick_roots(g, 64, seed=40)
+    for b in (8, 32, 64):
+        check_batch(g, dg, pool[:b])

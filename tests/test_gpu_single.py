@@ -1,0 +1,189 @@
+"""GPU parity of single-root BFS (bfs_run through the C ABI) against the oracle:
+levels identical, parents valid (V1-V4), run statistics equal to the oracle's."""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+import paper_1604_02844_amd as bfs
+from tests import pins
+from tests.gpu_helpers import check_root, gpu_run, load, torch_mod
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _cuda():
+    torch = torch_mod()
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    bfs.load_library()
+
+
+def test_closed_forms():
+    for g, r, exp_lv, exp_par in pins.closed_form_cases():
+        dg = load(g)
+        lv, pa, _ = check_root(g, dg, r, expected_levels=exp_lv)
+        if exp_par is not None:  # parent unique: must match exactly
+            assert np.array_equal(pa, exp_par), g.name
+
+
+def test_paper_examples():
+    ex = pins.load_golden("paper_examples.json")
+    race = ex["benign_race"]
+    g = graphgen.from_edges(race["n"], *zip(*race["edges"]))
+    lv, pa, _ = check_root(g, load(g), race["root"])
+    assert pa[race["vertex"]] in race["valid_parents"]
+    word = ex["bit_race_word"]
+    g = graphgen.from_edges(word["n"], [word["root"]] * len(word["children"]), word["children"])
+    lv, pa, _ = check_root(g, load(g), word["root"])
+    assert all(lv[c] == 1 and pa[c] == word["root"] for c in word["children"])
+
+
+def test_bitmap_layout_word_boundaries():
+    """Vertices on both sides of 32-bit word boundaries (section 3.3.1 layout)."""
+    n = 64 * 33 + 5
+    v = np.arange(n - 1)
+    g = graphgen.path(n)
+    for r in (0, 31, 32, 63, 64, n - 1):
+        check_root(g, load(g), r, expected_levels=np.abs(np.arange(n) - r))
+
+
+def test_degenerate_graphs():
+    g = graphgen.empty(1)
+    lv, pa, st = gpu_run(load(g), 0)
+    assert lv.tolist() == [0] and pa.tolist() == [0] and st["num_levels"] == 1
+    g = graphgen.empty(100)
+    lv, pa, st = gpu_run(load(g), 57)
+    assert lv[57] == 0 and (lv >= 0).sum() == 1 and pa[57] == 57
+    g = graphgen.disjoint(graphgen.star(40), graphgen.empty(3))
+    check_root(g, load(g), 41)  # isolated root
+    check_root(g, load(g), 5)
+
+
+def test_self_loops_duplicates_unsorted_rows():
+    rng = np.random.default_rng(5)
+    n = 3000
+    src = rng.integers(0, n, 20000)
+    dst = rng.integers(0, n, 20000)
+    g = graphgen.from_edges(n, np.r_[src, src[:500], np.arange(0, n, 7)], np.r_[dst, dst[:500], np.arange(0, n, 7)],
+                            symmetric=False, dedupe=False, drop_self_loops=False, sort_rows=False)
+    dg = load(g)
+    for r in (0, 1, 1234):
+        check_root(g, dg, r, rows_sorted=False)
+
+
+@pytest.mark.parametrize("offsets_i32", [True, False])
+def test_rmat_scale10_int32_csr(offsets_i32):
+    """Kronecker scale 10, edgefactor 16, 16 seeded roots (the small R-MAT workload)."""
+    g = graphgen.rmat(10, 16, seed=1)
+    dg = load(g, offsets_i32=offsets_i32)
+    for r in graphgen.pick_roots(g, 16, seed=2):
+        check_root(g, dg, int(r))
+
+
+def test_device_pointer_graph():
+    g = graphgen.rmat(12, 16, seed=3)
+    dg = load(g, device_ptrs=True)
+    for r in graphgen.pick_roots(g, 4, seed=4):
+        check_root(g, dg, int(r))
+
+
+@pytest.mark.parametrize("tun", [
+    dict(small_max_degree=1, wave_max_degree=1),                # everything grid-split or per-wavefront
+    dict(small_max_degree=64, wave_max_degree=64),              # packed + grid-split rows
+    dict(small_max_degree=4, wave_max_degree=100000),           # packed + wavefront, no grid split
+    dict(small_max_degree=8, wave_max_degree=32),
+    dict(small_max_degree=16, wave_max_degree=256, update_mode=2),   # atomicOr claims
+    dict(small_max_degree=1, wave_max_degree=1, update_mode=2),
+    dict(block_size=512, blocks_per_cu=1),
+    dict(block_size=256, blocks_per_cu=2, update_mode=2),
+    dict(block_size=512, blocks_per_cu=1, update_mode=1),
+])
+def test_bins_and_launch_shapes(tun):
+    """Correctness does not depend on the degree bins or the launch shape."""
+    g = graphgen.rmat(14, 16, seed=7)
+    dg = load(g)
+    bfs.bfs_graph_set_tunables(dg, **tun)
+    for r in graphgen.pick_roots(g, 3, seed=8):
+        check_root(g, dg, int(r))
+
+
+def test_erdos_renyi():
+    g = graphgen.er(1 << 16, 8, seed=9)
+    dg = load(g)
+    for r in graphgen.pick_roots(g, 4, seed=10):
+        check_root(g, dg, int(r))
+
+
+def test_contention_stress():
+    """Many claimants for the same words: complete graph, star, dense id blocks."""
+    for g in (graphgen.complete(300), graphgen.star(5000), graphgen.grid(64, 64)):
+        dg = load(g)
+        check_root(g, dg, 0)
+        check_root(g, dg, g.n - 1)
+    n = 4096
+    a = np.repeat(np.arange(0, 64), 64)
+    b = np.tile(np.arange(64, 128), 64)
+    g = graphgen.from_edges(n, a, b)
+    check_root(g, load(g), 0)
+
+
+@pytest.mark.parametrize("update_mode", [1, 2])
+def test_update_modes_scale16(update_mode):
+    """Both bitmap update schemes (restoration and atomicOr) give exact levels."""
+    g = graphgen.rmat(16, 16, seed=21)
+    dg = load(g)
+    bfs.bfs_graph_set_tunables(dg, update_mode=update_mode)
+    for r in graphgen.pick_roots(g, 4, seed=22):
+        check_root(g, dg, int(r))
+
+
+def test_levels_deterministic_across_runs():
+    g = graphgen.rmat(16, 16, seed=11)
+    dg = load(g)
+    r = int(graphgen.pick_roots(g, 1, seed=12)[0])
+    first, _, _ = gpu_run(dg, r)
+    for _ in range(5):
+        lv, pa, _ = gpu_run(dg, r)
+        assert np.array_equal(lv, first)
+
+
+def test_host_output_and_async_stream():
+    torch = torch_mod()
+    g = graphgen.rmat(12, 16, seed=13)
+    dg = load(g)
+    r = int(graphgen.pick_roots(g, 1, seed=14)[0])
+    ref, _, _ = oracle.bfs(g.offsets, g.cols, r)
+    lv = np.empty(g.n, dtype=np.int32)
+    pa = np.empty(g.n, dtype=np.int32)
+    bfs.bfs_run(dg, r, lv, pa)  # BFS_OUT_HOST
+    assert oracle.validate(g.offsets, g.cols, r, ref, lv, pa)[0] == 0
+    s = torch.cuda.Stream()
+    lvd = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    pad = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    with torch.cuda.stream(s):
+        assert bfs.bfs_run(dg, r, lvd, pad, stream=s, flags=bfs.BFS_ASYNC) is None
+    s.synchronize()
+    assert oracle.validate(g.offsets, g.cols, r, ref, lvd.cpu().numpy(), pad.cpu().numpy())[0] == 0
+
+
+def test_run_errors():
+    torch = torch_mod()
+    g = graphgen.path(10)
+    dg = load(g)
+    lv = torch.empty(10, dtype=torch.int32, device="cuda")
+    for bad in (-1, 10):
+        with pytest.raises(bfs.BfsError) as e:
+            bfs.bfs_run(dg, bad, lv, lv)
+        assert e.value.status == bfs.BFS_E_ROOT_RANGE
+    with pytest.raises(bfs.BfsError) as e:
+        bfs.bfs_run(dg, 0, lv, lv, flags=bfs.BFS_ASYNC | 0x80)
+    assert e.value.status == bfs.BFS_E_INVALID_ARG
+
+
+def test_rmat_scale20_64_roots():
+    """R-MAT scale 20, edgefactor 16, int64 offsets, the 64 seeded roots."""
+    g = graphgen.cached("rmat", scale=20, edgefactor=16, seed=1)
+    dg = load(g)
+    for r in graphgen.pick_roots(g, 64, seed=2):
+        check_root(g, dg, int(r))

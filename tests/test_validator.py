@@ -59,3 +59,34 @@ def test_rejects_mutations(case):
         assert oracle.validate(g.offsets, g.cols, r, lv, lv, p) == (4, v)
     p = pa.copy(); p[v] = g.n + 3
     assert oracle.validate(g.offsets, g.cols, r, lv, lv, p)[0] == 4
+
+
+def test_certify_accepts_valid_and_rejects_mutations(case):
+    """V2-V5 without oracle levels accept exactly the hop distances."""
+    g, r, lv, pa = case
+    assert oracle.certify(g.offsets, g.cols, r, lv, pa) == (0, -1)
+    reached = np.nonzero(lv > 0)[0]
+    v = int(reached[len(reached) // 2])
+    m = lv.copy(); m[v] += 1          # too far: its parent is no longer one level up
+    assert oracle.certify(g.offsets, g.cols, r, m, pa)[0] in (4, 5)
+    m = lv.copy(); m[v] -= 1          # too close
+    assert oracle.certify(g.offsets, g.cols, r, m, pa)[0] in (4, 5)
+    m = lv.copy(); p = pa.copy(); m[v] = -1; p[v] = -1   # dropped reached vertex
+    assert oracle.certify(g.offsets, g.cols, r, m, p)[0] in (4, 5)
+    m = np.where(lv > 0, lv * 2, lv).astype(np.int32)   # every level doubled
+    assert oracle.certify(g.offsets, g.cols, r, m, pa)[0] != 0
+
+
+def test_certify_agrees_with_validate_on_small_graphs():
+    rng = np.random.default_rng(17)
+    for _ in range(60):
+        n = int(rng.integers(2, 40))
+        g = graphgen.from_edges(n, rng.integers(0, n, 3 * n), rng.integers(0, n, 3 * n))
+        r = int(rng.integers(0, n))
+        lv, pa, _ = oracle.bfs(g.offsets, g.cols, r)
+        assert oracle.certify(g.offsets, g.cols, r, lv, pa)[0] == 0
+        if lv.max() >= 1:
+            m = lv.copy()
+            far = lv == lv.max()
+            m[far] = lv.max() + 1     # the deepest layer pushed one level further
+            assert oracle.certify(g.offsets, g.cols, r, m, pa)[0] != 0

@@ -132,6 +132,10 @@ int bfs_graph_set_tunables(bfs_graph* g, const bfs_tunables* t) {
             bfs::hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
             std::lock_guard<std::mutex> lk(g->mu);
             bfs::rebuild_big(g, r.wave_max_degree);
+            // Workspaces hold lists sized for the old table: drop them.
+            for (auto* w : g->ws_all) g->device_bytes -= w->bytes;
+            for (auto* w : g->ms_all) g->device_bytes -= w->bytes;
+            bfs::free_workspaces(g);
         }
         g->tun = r;
         return BFS_OK;

@@ -32,6 +32,7 @@ constexpr int kStripeStride = 16;  // u64 per stripe (128 bytes)
 // double-buffered by level parity.
 struct Ctrl {
     unsigned long long newcnt[2][kStripes * kStripeStride];  // vertices found per level
+    unsigned long long bigarcs[2][kStripes * kStripeStride]; // arcs of the level's big rows
     unsigned long long reached;    // totals, written by the final stats kernel
     unsigned long long arcs;
     unsigned long long alive[3];   // multi-source: OR of new root bits per level (ring)
@@ -52,6 +53,13 @@ struct Workspace {
     Ctrl* ctrl = nullptr;
     unsigned long long* slots = nullptr;  // per-block partial sums (arcs | reached)
     int64_t nslots = 0;
+    // Frontier rows above T2, compacted by the restore pass into one segment per
+    // restore block: row ids, arc offsets within the segment, segment totals.
+    int32_t* bl_u = nullptr;
+    uint32_t* bl_pre = nullptr;
+    uint32_t* seg_cnt = nullptr;
+    uint32_t* seg_arcs = nullptr;
+    int32_t big_capacity = 0;
     Ctrl* host_ctrl = nullptr;      // pinned mirror for stats
     int32_t* out_levels = nullptr;  // staging for BFS_OUT_HOST
     int32_t* out_parents = nullptr;
@@ -118,6 +126,9 @@ struct bfs_graph {
     int32_t* d_big = nullptr;
     int64_t* d_big_prefix = nullptr;
     uint32_t* d_bigmap = nullptr;
+    // Restore grid and where each restore block's big-row segment starts.
+    int32_t restore_grid = 0;
+    int32_t* d_seg_start = nullptr;
 
     bfs_tunables tun{};
     std::mutex mu;
@@ -134,6 +145,10 @@ namespace bfs {
 bfs_tunables default_tunables(const bfs_graph* g);
 bfs_tunables resolve_tunables(const bfs_graph* g, const bfs_tunables& t);
 void rebuild_big(bfs_graph* g, int32_t threshold);
+int64_t padded_words(int64_t n);
+// Blocks of the restore pass: 256-word chunks, chunk c handled by block c % grid.
+constexpr int kRestoreBlock = 256;
+int restore_grid_for(int64_t words, int cu_count);
 
 Workspace* acquire_ws(bfs_graph* g, hipStream_t s);
 void release_ws(bfs_graph* g, Workspace* w, hipStream_t s);
@@ -157,9 +172,15 @@ void ms_reset(bfs_graph* g, MsWorkspace* w, hipStream_t s);
 // already be in w->ctrl.
 void ms_join(bfs_graph* g, MsWorkspace* w, const int32_t* slots, const int32_t* roots, int32_t count, int level,
              hipStream_t s);
-// Expand one level of the instance; returns after the step's summary is on the
-// host (w->host_ctrl->sum_*). `level` is the instance level being expanded.
-void ms_step(bfs_graph* g, const bfs_tunables& t, MsWorkspace* w, int level, hipStream_t s, bool per_slot);
+// Enqueue one level of the instance on `s` plus an asynchronous copy of the
+// step summary (sum_*, per-slot totals) into w->host_ctrl; the caller
+// synchronises `s` before reading it. `level` is the instance level expanded.
+void ms_step_enqueue(bfs_graph* g, const bfs_tunables& t, MsWorkspace* w, int level, hipStream_t s,
+                     bool per_slot);
+// Point slot `slot` at its output rows and start level (host-side staging in
+// `staging`, a pinned MsCtrl that must stay untouched until `s` has drained).
+void ms_set_slot(MsWorkspace* w, MsCtrl* staging, int slot, int32_t* lv, int32_t* pa, int32_t start,
+                 hipStream_t s);
 void ms_retire(bfs_graph* g, MsWorkspace* w, unsigned long long keep, hipStream_t s);
 
 int device_cu_count(int device);

@@ -48,9 +48,14 @@ std::vector<int64_t> degrees_of(int64_t n, const OffT* off) {
 // Device-side CSR checks for borrowed device arrays (kernel in single.hip).
 void validate_device_csr(const void* off, bool off32, const int32_t* col, int64_t n, int64_t nnz);
 
-static int64_t padded_words(int64_t n) {
+int64_t padded_words(int64_t n) {
     int64_t words = (n + 31) / 32;
     return (words + 63) / 64 * 64;
+}
+
+int restore_grid_for(int64_t words, int cu_count) {
+    const int64_t chunks = (words + kRestoreBlock - 1) / kRestoreBlock;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(chunks, (int64_t)std::max(cu_count, 1) * 8));
 }
 
 // Table of rows with degree > threshold (split over the whole expansion grid)
@@ -61,9 +66,11 @@ void rebuild_big(bfs_graph* g, int32_t threshold) {
     if (g->d_big) BFS_HIP(hipFree(g->d_big));
     if (g->d_big_prefix) BFS_HIP(hipFree(g->d_big_prefix));
     if (g->d_bigmap) BFS_HIP(hipFree(g->d_bigmap));
+    if (g->d_seg_start) BFS_HIP(hipFree(g->d_seg_start));
     g->d_big = nullptr;
     g->d_big_prefix = nullptr;
     g->d_bigmap = nullptr;
+    g->d_seg_start = nullptr;
     g->big_threshold = threshold;
     g->num_big = 0;
     g->big_arcs = 0;
@@ -97,6 +104,17 @@ void rebuild_big(bfs_graph* g, int32_t threshold) {
     if (!big.empty()) BFS_HIP(hipMemcpy(g->d_big, big.data(), big.size() * 4, hipMemcpyHostToDevice));
     BFS_HIP(hipMemcpy(g->d_big_prefix, prefix.data(), prefix.size() * 8, hipMemcpyHostToDevice));
     BFS_HIP(hipMemcpy(g->d_bigmap, bigmap.data(), (size_t)words * 4, hipMemcpyHostToDevice));
+    // Segment capacities of the restore pass: the big rows inside the chunks
+    // that each restore block visits.
+    g->restore_grid = restore_grid_for(words, g->cu_count);
+    std::vector<int32_t> seg((size_t)g->restore_grid + 1, 0);
+    for (int64_t w = 0; w < words; ++w) {
+        const int b = (int)((w / kRestoreBlock) % g->restore_grid);
+        seg[(size_t)b + 1] += __builtin_popcount(bigmap[(size_t)w]);
+    }
+    for (int b = 0; b < g->restore_grid; ++b) seg[(size_t)b + 1] += seg[(size_t)b];
+    BFS_HIP(hipMalloc(&g->d_seg_start, seg.size() * 4));
+    BFS_HIP(hipMemcpy(g->d_seg_start, seg.data(), seg.size() * 4, hipMemcpyHostToDevice));
 }
 
 bfs_tunables default_tunables(const bfs_graph* g) {
@@ -150,8 +168,10 @@ Workspace* acquire_ws(bfs_graph* g, hipStream_t s) {
         w->device = g->device;
         w->words = padded_words(g->n);
         w->nslots = (int64_t)g->cu_count * 64 + 64;  // >= any expansion or restore grid
+        w->big_capacity = std::max(g->num_big, 1);
         const size_t bmb = (size_t)w->words * 4;
-        const size_t total = bmb * 3 + sizeof(Ctrl) + (size_t)w->nslots * 2 * 8;
+        const size_t listb = (size_t)w->big_capacity * 8 + (size_t)(g->restore_grid + 1) * 8;
+        const size_t total = bmb * 3 + sizeof(Ctrl) + (size_t)w->nslots * 2 * 8 + listb;
         char* base = nullptr;
         BFS_HIP(hipMalloc(&base, total));
         w->vis = reinterpret_cast<uint32_t*>(base);
@@ -159,6 +179,11 @@ Workspace* acquire_ws(bfs_graph* g, hipStream_t s) {
         w->fr = w->vis_prev + w->words;
         w->ctrl = reinterpret_cast<Ctrl*>(base + bmb * 3);
         w->slots = reinterpret_cast<unsigned long long*>(base + bmb * 3 + sizeof(Ctrl));
+        char* lp = base + bmb * 3 + sizeof(Ctrl) + (size_t)w->nslots * 2 * 8;
+        w->bl_u = reinterpret_cast<int32_t*>(lp);
+        w->bl_pre = reinterpret_cast<uint32_t*>(lp + (size_t)w->big_capacity * 4);
+        w->seg_cnt = reinterpret_cast<uint32_t*>(lp + (size_t)w->big_capacity * 8);
+        w->seg_arcs = w->seg_cnt + (g->restore_grid + 1);
         BFS_HIP(hipMemset(w->ctrl, 0, sizeof(Ctrl)));
         BFS_HIP(hipHostMalloc(&w->host_ctrl, sizeof(Ctrl), hipHostMallocDefault));
         BFS_HIP(hipEventCreate(&w->ev_start));
@@ -311,6 +336,7 @@ bfs_graph* load_csr(int64_t n, int64_t nnz, const void* offsets, const int32_t* 
         if (g->d_big) (void)hipFree(g->d_big);
         if (g->d_big_prefix) (void)hipFree(g->d_big_prefix);
         if (g->d_bigmap) (void)hipFree(g->d_bigmap);
+        if (g->d_seg_start) (void)hipFree(g->d_seg_start);
         delete g;
         throw;
     }
@@ -328,6 +354,7 @@ void free_graph(bfs_graph* g) {
     if (g->d_big) (void)hipFree(g->d_big);
     if (g->d_big_prefix) (void)hipFree(g->d_big_prefix);
     if (g->d_bigmap) (void)hipFree(g->d_bigmap);
+    if (g->d_seg_start) (void)hipFree(g->d_seg_start);
     delete g;
 }
 

@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 
 #include "bfs_internal.h"
 
@@ -625,12 +626,26 @@ void ms_join(bfs_graph* g, MsWorkspace* w, const int32_t* slots, const int32_t* 
     BFS_HIP(hipStreamSynchronize(s));
 }
 
-void ms_step(bfs_graph* g, const bfs_tunables& t, MsWorkspace* w, int level, hipStream_t s, bool per_slot) {
+void ms_step_enqueue(bfs_graph* g, const bfs_tunables& t, MsWorkspace* w, int level, hipStream_t s,
+                     bool per_slot) {
     enqueue_level_any(g, t, w, level, per_slot, s);
     k_ms_summary<<<1, 64, 0, s>>>(w->ctrl, level + 1);
     BFS_HIP(hipGetLastError());
-    BFS_HIP(hipMemcpyAsync(w->host_ctrl, w->ctrl, sizeof(MsCtrl), hipMemcpyDeviceToHost, s));
-    BFS_HIP(hipStreamSynchronize(s));
+    // Only the small tail of the control block (per-slot totals, summaries).
+    const size_t from = offsetof(MsCtrl, slot_reached);
+    BFS_HIP(hipMemcpyAsync(reinterpret_cast<char*>(w->host_ctrl) + from, reinterpret_cast<char*>(w->ctrl) + from,
+                           sizeof(MsCtrl) - from, hipMemcpyDeviceToHost, s));
+}
+
+void ms_set_slot(MsWorkspace* w, MsCtrl* staging, int slot, int32_t* lv, int32_t* pa, int32_t start,
+                 hipStream_t s) {
+    if (slot < 0 || slot >= 64) fail(BFS_E_INTERNAL, "slot out of range");
+    staging->out_lv[slot] = lv;
+    staging->out_pa[slot] = pa;
+    staging->start[slot] = start;
+    BFS_HIP(hipMemcpyAsync(&w->ctrl->out_lv[slot], &staging->out_lv[slot], sizeof(int32_t*), hipMemcpyHostToDevice, s));
+    BFS_HIP(hipMemcpyAsync(&w->ctrl->out_pa[slot], &staging->out_pa[slot], sizeof(int32_t*), hipMemcpyHostToDevice, s));
+    BFS_HIP(hipMemcpyAsync(&w->ctrl->start[slot], &staging->start[slot], sizeof(int32_t), hipMemcpyHostToDevice, s));
 }
 
 void ms_retire(bfs_graph* g, MsWorkspace* w, unsigned long long keep, hipStream_t s) {

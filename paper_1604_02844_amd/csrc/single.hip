@@ -27,11 +27,13 @@
 //              mbcnt into an LDS ring (dense batches of 64), reads row bounds,
 //              expands rows of degree <= T1 packed across the lanes (prefix sum
 //              + binary search) and rows with T1 < d <= T2 one wavefront each.
-//              Rows with d > T2 are listed once at load time and their
-//              concatenated arcs are split evenly over all workgroups (one
-//              workgroup per row, several for hubs).
+//              Frontier rows with d > T2 come from a list that the previous
+//              restore pass compacted; their concatenated arcs are split evenly
+//              over all workgroups (one workgroup per row, several for hubs).
 //   k_restore  exact next-layer bits per touched word, visited snapshot,
-//              next frontier bitmap, per-level discovered count.
+//              next frontier bitmap, per-level discovered count, and the list
+//              of the next frontier's big rows: one segment per restore block,
+//              placed with a workgroup prefix sum (no atomics).
 // Levels are enqueued in chunks; the host reads a done flag between chunks.
 #include <hip/hip_runtime.h>
 
@@ -59,13 +61,17 @@ struct SingleParams {
     Ctrl* ctrl;
     unsigned long long* arcs_slot;     // per expansion block
     unsigned long long* reached_slot;  // per restore block
-    const int32_t* big;
-    const int64_t* big_prefix;
-    const uint32_t* bigmap;
-    int32_t num_big;
-    int64_t big_arcs;
+    const uint32_t* bigmap;   // rows with degree > T2
+    int32_t* bl_u;            // big frontier rows, one segment per restore block
+    uint32_t* bl_pre;         // their exclusive arc offsets within the segment
+    uint32_t* seg_cnt;        // rows per segment
+    uint32_t* seg_arcs;       // arcs per segment
+    const int32_t* seg_start; // first list slot of each segment
+    int32_t restore_grid;
     int32_t t1;
 };
+
+constexpr int kMinBigShare = 1024;  // fewest big-row arcs handed to one workgroup
 
 __device__ __forceinline__ int rank_in(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
@@ -94,6 +100,25 @@ __device__ __forceinline__ int64_t shfl64(int64_t x, int src) {
     int lo = __shfl((int)(uint32_t)(uint64_t)x, src, 64);
     int hi = __shfl((int)(uint32_t)((uint64_t)x >> 32), src, 64);
     return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Exclusive prefix sum over a workgroup of BLOCK threads; returns the total.
+template <int BLOCK>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t& excl, uint32_t* tmp) {
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int incl = wave_incl_scan((int)x, lane);
+    if (lane == 63) tmp[wid] = (uint32_t)incl;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+#pragma unroll
+    for (int i = 0; i < BLOCK / 64; ++i) {
+        const uint32_t t = tmp[i];
+        if (i < wid) before += t;
+        total += t;
+    }
+    __syncthreads();
+    excl = before + (uint32_t)incl - x;
+    return total;
 }
 
 template <typename OffT>
@@ -215,15 +240,20 @@ __device__ __forceinline__ void process_batch(const SingleParams& p, int32_t u, 
     }
 }
 
+constexpr int kMaxRestoreGrid = 2048;
+
 template <int BLOCK>
 struct ExpandShared {
     static constexpr int NW = BLOCK / 64;
     uint32_t ring[NW][128];
-    int32_t active[BLOCK];
-    int nactive;
-    int big_first;
+    uint32_t segpre[kMaxRestoreGrid + 1];  // exclusive prefix of segment arcs
+    uint32_t tmp[BLOCK / 64];
     unsigned long long red[NW];
     unsigned long long found;
+    unsigned long long big_total;
+    int64_t row_beg;   // broadcast of the big row being expanded
+    int64_t row_len;
+    int32_t row_u;
 };
 
 // a0: levels/parents = -1, bitmaps cleared, root seeded, counters reset.
@@ -265,8 +295,24 @@ __global__ __launch_bounds__(BLOCK) void k_init(SingleParams p, int nslots) {
         p.arcs_slot[i] = 0;
         p.reached_slot[i] = 0;
     }
-    for (int64_t i = gtid; i < 2 * kStripes; i += gsize)
+    // The root is the whole first frontier; when its row is big it is the only
+    // entry of the big-row list (in the segment of its restore block).
+    const bool root_big = (p.bigmap[rw] >> (p.root & 31)) & 1u;
+    const int root_seg = (int)((rw / kRestoreBlock) % p.restore_grid);
+    const int64_t root_deg = load_off<OffT>(p.off, (int64_t)p.root + 1) - load_off<OffT>(p.off, p.root);
+    for (int64_t i = gtid; i < p.restore_grid; i += gsize) {
+        const bool here = root_big && i == root_seg;
+        p.seg_cnt[i] = here ? 1u : 0u;
+        p.seg_arcs[i] = here ? (uint32_t)root_deg : 0u;
+        if (here) {
+            p.bl_u[p.seg_start[i]] = p.root;
+            p.bl_pre[p.seg_start[i]] = 0;
+        }
+    }
+    for (int64_t i = gtid; i < 2 * kStripes; i += gsize) {
         *stripe(p.ctrl, (int)(i / kStripes), (int)(i % kStripes)) = (i == 0) ? 1ull : 0ull;
+        p.ctrl->bigarcs[i / kStripes][(i % kStripes) * kStripeStride] = (i == 0 && root_big) ? (unsigned long long)root_deg : 0ull;
+    }
     if (gtid == 0) {
         p.ctrl->done = 0;
         p.ctrl->num_levels = 0;
@@ -301,44 +347,94 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl) {
     }
     unsigned long long arcs = 0;
 
-    // ---- rows of degree > T2: this block's slice of their concatenated arcs
-    if (p.num_big > 0) {
-        const int64_t per = (p.big_arcs + G - 1) / G;
-        const int64_t s0 = bid * per;
-        const int64_t s1 = s0 + per < p.big_arcs ? s0 + per : p.big_arcs;
-        if (s0 < s1) {
-            if (tid == 0) {
-                int lo = 0, hi = p.num_big;  // first row h with big_prefix[h+1] > s0
-                while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
-                    if (p.big_prefix[mid + 1] > s0)
-                        hi = mid;
-                    else
-                        lo = mid + 1;
-                }
-                sh.big_first = lo;
+    // ---- rows of degree > T2: the level's big-row arcs, split evenly
+    if (tid < 64) {
+        unsigned long long c = p.ctrl->bigarcs[lvl & 1][tid * kStripeStride];
+        c = wave_sum(c);
+        if (tid == 0) sh.big_total = c;
+        if (bid == 0) p.ctrl->bigarcs[(lvl + 1) & 1][tid * kStripeStride] = 0;
+    }
+    __syncthreads();
+    const int64_t ta = (int64_t)sh.big_total;
+    if (ta > 0) {
+        int64_t per = (ta + G - 1) / G;
+        if (per < kMinBigShare) per = kMinBigShare;
+        const int64_t a0 = bid * per;
+        const int64_t a1 = a0 + per < ta ? a0 + per : ta;
+        if (a0 < a1) {
+            // Exclusive prefix of the segment totals (one segment per restore block).
+            const int R = p.restore_grid;
+            constexpr int PER_T = (kMaxRestoreGrid + BLOCK - 1) / BLOCK;
+            uint32_t vals[PER_T];
+            uint32_t mine = 0;
+#pragma unroll
+            for (int k = 0; k < PER_T; ++k) {
+                const int i = tid * PER_T + k;
+                vals[k] = i < R ? p.seg_arcs[i] : 0u;
+                mine += vals[k];
+            }
+            uint32_t excl;
+            block_excl_scan<BLOCK>(mine, excl, sh.tmp);
+#pragma unroll
+            for (int k = 0; k < PER_T; ++k) {
+                const int i = tid * PER_T + k;
+                if (i <= R) sh.segpre[i] = excl;
+                excl += vals[k];
             }
             __syncthreads();
-            for (int h0 = sh.big_first; h0 < p.num_big && p.big_prefix[h0] < s1; h0 += BLOCK) {
-                // Which of the next BLOCK overlapping rows are in the frontier?
-                if (tid == 0) sh.nactive = 0;
-                __syncthreads();
-                const int h = h0 + tid;
-                if (h < p.num_big && p.big_prefix[h] < s1) {
-                    const int32_t u = p.big[h];
-                    if ((p.fr[u >> 5] >> (u & 31)) & 1u) sh.active[atomicAdd(&sh.nactive, 1)] = h;
+            // Walk the rows covering [a0, a1): thread 0 locates each piece, the
+            // whole workgroup expands it.
+            int seg = 0, idx = 0;
+            if (tid == 0) {
+                int lo = 0, hi = R - 1;  // last segment with segpre <= a0
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if ((int64_t)sh.segpre[mid] <= a0)
+                        lo = mid;
+                    else
+                        hi = mid - 1;
+                }
+                while (lo < R - 1 && (int64_t)sh.segpre[lo + 1] <= a0) ++lo;
+                seg = lo;
+                const int64_t local = a0 - (int64_t)sh.segpre[seg];
+                const int first = p.seg_start[seg];
+                int l2 = 0, h2 = (int)p.seg_cnt[seg] - 1;  // last row with offset <= local
+                while (l2 < h2) {
+                    const int mid = (l2 + h2 + 1) >> 1;
+                    if ((int64_t)p.bl_pre[first + mid] <= local)
+                        l2 = mid;
+                    else
+                        h2 = mid - 1;
+                }
+                idx = l2;
+            }
+            int64_t pos = a0;
+            while (pos < a1) {
+                if (tid == 0) {
+                    while (seg < R && idx >= (int)p.seg_cnt[seg]) {  // next non-empty segment
+                        ++seg;
+                        idx = 0;
+                    }
+                }
+                if (tid == 0 && seg >= R) sh.row_len = 0;  // list exhausted (cannot happen: a1 <= total)
+                if (tid == 0 && seg < R) {
+                    const int slot = p.seg_start[seg] + idx;
+                    const int32_t u = p.bl_u[slot];
+                    const int64_t row_start = (int64_t)sh.segpre[seg] + p.bl_pre[slot];
+                    const int64_t beg = load_off<OffT>(p.off, u);
+                    const int64_t deg = load_off<OffT>(p.off, (int64_t)u + 1) - beg;
+                    const int64_t end = row_start + deg < a1 ? row_start + deg : a1;
+                    sh.row_u = u;
+                    sh.row_beg = beg + (pos - row_start);
+                    sh.row_len = end - pos;
+                    ++idx;
                 }
                 __syncthreads();
-                const int na = sh.nactive;
-                for (int i = 0; i < na; ++i) {
-                    const int hh = sh.active[i];
-                    const int64_t a0 = s0 > p.big_prefix[hh] ? s0 : p.big_prefix[hh];
-                    const int64_t a1 = s1 < p.big_prefix[hh + 1] ? s1 : p.big_prefix[hh + 1];
-                    const int32_t u = p.big[hh];
-                    if (tid == 0) arcs += (unsigned long long)(a1 - a0);
-                    const int64_t beg = load_off<OffT>(p.off, u) + (a0 - p.big_prefix[hh]);
-                    expand_row<kAtomic, kUnroll>(p, beg, a1 - a0, u, tid, BLOCK, lvl + 1);
-                }
+                const int64_t len = sh.row_len;
+                if (len <= 0) break;
+                expand_row<kAtomic, kUnroll>(p, sh.row_beg, len, sh.row_u, tid, BLOCK, lvl + 1);
+                if (tid == 0) arcs += (unsigned long long)len;
+                pos += len;
                 __syncthreads();
             }
         }
@@ -390,47 +486,79 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl) {
 }
 
 // Restoration of level `lvl`: exact new bits per touched word, visited snapshot,
-// next frontier bitmap and the discovered count (striped).
-template <int BLOCK, bool kAtomic>
-__global__ __launch_bounds__(BLOCK) void k_restore(SingleParams p, int lvl) {
+// next frontier bitmap, the discovered count (striped), and the compacted list
+// of the next frontier's rows above T2 (this block's segment).
+template <typename OffT, bool kAtomic>
+__global__ __launch_bounds__(kRestoreBlock) void k_restore(SingleParams p, int lvl) {
+    constexpr int BLOCK = kRestoreBlock;
     __shared__ unsigned long long red[BLOCK / 64];
+    __shared__ uint32_t tmp[BLOCK / 64];
     if (p.ctrl->done) return;
     const int tid = threadIdx.x;
     const int64_t G = gridDim.x, bid = blockIdx.x;
     const int next = lvl + 1;
     unsigned long long found = 0;
-    for (int64_t w = bid * BLOCK + tid; w < p.words; w += G * BLOCK) {
-        const uint32_t cur = p.vis[w];
-        const uint32_t prev = p.vis_prev[w];
+    uint32_t seg_n = 0, seg_a = 0;  // running totals of this block's segment
+    const int32_t first = p.seg_start[bid];
+    for (int64_t c = bid; c * BLOCK < p.words; c += G) {
+        const int64_t w = c * BLOCK + tid;
         uint32_t exact = 0;
-        if (cur != prev) {
-            if (kAtomic) {
-                exact = cur & ~prev;
-            } else {
-                // A racing read-modify-write may have dropped bits of this level,
-                // never added foreign ones, and always leaves one of its bits:
-                // the level array says exactly who was discovered.
-                const int64_t v0 = w * 32;
-                if (v0 + 32 <= p.n && (reinterpret_cast<uintptr_t>(p.levels) & 15) == 0) {
-                    const int4* l4 = reinterpret_cast<const int4*>(p.levels + v0);
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        const int4 x = l4[q];
-                        exact |= (uint32_t)(x.x == next) << (4 * q);
-                        exact |= (uint32_t)(x.y == next) << (4 * q + 1);
-                        exact |= (uint32_t)(x.z == next) << (4 * q + 2);
-                        exact |= (uint32_t)(x.w == next) << (4 * q + 3);
-                    }
+        if (w < p.words) {
+            const uint32_t cur = p.vis[w];
+            const uint32_t prev = p.vis_prev[w];
+            if (cur != prev) {
+                if (kAtomic) {
+                    exact = cur & ~prev;
                 } else {
-                    for (int b = 0; b < 32 && v0 + b < p.n; ++b) exact |= (uint32_t)(p.levels[v0 + b] == next) << b;
+                    // A racing read-modify-write may have dropped bits of this
+                    // level, never added foreign ones, and always leaves one of
+                    // its bits: the level array says exactly who was discovered.
+                    const int64_t v0 = w * 32;
+                    if (v0 + 32 <= p.n && (reinterpret_cast<uintptr_t>(p.levels) & 15) == 0) {
+                        const int4* l4 = reinterpret_cast<const int4*>(p.levels + v0);
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) {
+                            const int4 x = l4[q];
+                            exact |= (uint32_t)(x.x == next) << (4 * q);
+                            exact |= (uint32_t)(x.y == next) << (4 * q + 1);
+                            exact |= (uint32_t)(x.z == next) << (4 * q + 2);
+                            exact |= (uint32_t)(x.w == next) << (4 * q + 3);
+                        }
+                    } else {
+                        for (int b = 0; b < 32 && v0 + b < p.n; ++b)
+                            exact |= (uint32_t)(p.levels[v0 + b] == next) << b;
+                    }
                 }
+                const uint32_t nv = prev | exact;
+                if (cur != nv) p.vis[w] = nv;
+                p.vis_prev[w] = nv;
             }
-            const uint32_t nv = prev | exact;
-            if (cur != nv) p.vis[w] = nv;
-            p.vis_prev[w] = nv;
+            p.fr[w] = exact;
+            found += (unsigned long long)__popc(exact);
         }
-        p.fr[w] = exact;
-        found += (unsigned long long)__popc(exact);
+        // Append the next frontier's big rows of this chunk to the segment.
+        const uint32_t big = w < p.words ? (exact & p.bigmap[w]) : 0u;
+        uint32_t my_arcs = 0;
+        for (uint32_t x = big; x; x &= x - 1) {
+            const int64_t u = w * 32 + __builtin_ctz(x);
+            my_arcs += (uint32_t)(load_off<OffT>(p.off, u + 1) - load_off<OffT>(p.off, u));
+        }
+        uint32_t cnt_excl, arc_excl;
+        const uint32_t cnt_tot = block_excl_scan<BLOCK>((uint32_t)__popc(big), cnt_excl, tmp);
+        const uint32_t arc_tot = block_excl_scan<BLOCK>(my_arcs, arc_excl, tmp);
+        if (big) {
+            uint32_t slot = first + seg_n + cnt_excl;
+            uint32_t at = seg_a + arc_excl;
+            for (uint32_t x = big; x; x &= x - 1) {
+                const int64_t u = w * 32 + __builtin_ctz(x);
+                p.bl_u[slot] = (int32_t)u;
+                p.bl_pre[slot] = at;
+                at += (uint32_t)(load_off<OffT>(p.off, u + 1) - load_off<OffT>(p.off, u));
+                ++slot;
+            }
+        }
+        seg_n += cnt_tot;
+        seg_a += arc_tot;
     }
     found = wave_sum(found);
     if ((tid & 63) == 0) red[tid >> 6] = found;
@@ -442,6 +570,9 @@ __global__ __launch_bounds__(BLOCK) void k_restore(SingleParams p, int lvl) {
             atomicAdd(stripe(p.ctrl, next & 1, (int)(bid % kStripes)), a);
             p.reached_slot[bid] += a;
         }
+        p.seg_cnt[bid] = seg_n;
+        p.seg_arcs[bid] = seg_a;
+        if (seg_a) atomicAdd(&p.ctrl->bigarcs[next & 1][(bid % kStripes) * kStripeStride], (unsigned long long)seg_a);
     }
 }
 
@@ -501,19 +632,19 @@ struct Grids {
 };
 
 template <typename OffT, int BLOCK, bool kAtomic>
-Grids grids_for(bfs_graph* g, const bfs_tunables& t, int64_t words, int64_t nslots) {
+Grids grids_for(bfs_graph* g, const bfs_tunables& t, int64_t nslots) {
     static const int occ = occupancy_of(k_expand<OffT, BLOCK, kAtomic>, BLOCK);
     const int bpc = t.blocks_per_cu > 0 && (occ < 1 || t.blocks_per_cu < occ) ? t.blocks_per_cu : (occ > 0 ? occ : 1);
     int64_t ge = (int64_t)bpc * g->cu_count;
-    int64_t gr = std::min<int64_t>((words + 255) / 256, (int64_t)g->cu_count * 8);
     ge = std::max<int64_t>(1, std::min(ge, nslots));
-    gr = std::max<int64_t>(1, std::min(gr, nslots));
-    return Grids{(int)ge, (int)gr};
+    if (g->restore_grid < 1 || g->restore_grid > kMaxRestoreGrid || g->restore_grid > nslots)
+        fail(BFS_E_INTERNAL, "restore grid out of range");
+    return Grids{(int)ge, g->restore_grid};
 }
 
 template <typename OffT, int BLOCK, bool kAtomic>
 void launch_typed(bfs_graph* g, const bfs_tunables& t, Workspace* w, SingleParams& p, hipStream_t s) {
-    const Grids gr = grids_for<OffT, BLOCK, kAtomic>(g, t, p.words, w->nslots);
+    const Grids gr = grids_for<OffT, BLOCK, kAtomic>(g, t, w->nslots);
     const int init_grid = (int)std::min<int64_t>(std::max<int64_t>(p.n / 4, p.words) / BLOCK + 1, 4096);
     k_init<OffT, BLOCK><<<init_grid, BLOCK, 0, s>>>(p, (int)w->nslots);
     BFS_HIP(hipGetLastError());
@@ -523,7 +654,7 @@ void launch_typed(bfs_graph* g, const bfs_tunables& t, Workspace* w, SingleParam
     while (true) {
         for (int i = 0; i < chunk; ++i) {
             k_expand<OffT, BLOCK, kAtomic><<<gr.expand, BLOCK, 0, s>>>(p, lvl + i);
-            k_restore<256, kAtomic><<<gr.restore, 256, 0, s>>>(p, lvl + i);
+            k_restore<OffT, kAtomic><<<gr.restore, kRestoreBlock, 0, s>>>(p, lvl + i);
         }
         BFS_HIP(hipGetLastError());
         lvl += chunk;
@@ -557,12 +688,15 @@ void launch_single(bfs_graph* g, const bfs_tunables& t, Workspace* w, int32_t ro
     p.ctrl = w->ctrl;
     p.arcs_slot = w->slots;
     p.reached_slot = w->slots + w->nslots;
-    p.big = g->d_big;
-    p.big_prefix = g->d_big_prefix;
     p.bigmap = g->d_bigmap;
-    p.num_big = g->num_big;
-    p.big_arcs = g->big_arcs;
+    p.bl_u = w->bl_u;
+    p.bl_pre = w->bl_pre;
+    p.seg_cnt = w->seg_cnt;
+    p.seg_arcs = w->seg_arcs;
+    p.seg_start = g->d_seg_start;
+    p.restore_grid = g->restore_grid;
     p.t1 = t.small_max_degree;
+    if (w->big_capacity < g->num_big) fail(BFS_E_INTERNAL, "big-row list too small");
     const bool atomic = t.update_mode == 2;
 #define BFS_LAUNCH(OFFT, BS)                                         \
     do {                                                             \

@@ -56,6 +56,18 @@ struct MsParams {
     int32_t t1;
 };
 
+// Cross-kernel shared state (masks, statistics, slot table) is accessed with
+// device-scope loads and stores: each XCD has its own L2, and a plain load may
+// otherwise hit a line another XCD rewrote in an earlier kernel.
+template <typename T>
+__device__ __forceinline__ T ld(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ __forceinline__ int rank_in(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
 }
@@ -113,9 +125,9 @@ __device__ __forceinline__ LevelView read_level(MsCtrl* c, int lvl) {
     const int tid = threadIdx.x;
     if (tid < 64) {
         const int par = lvl & 1;
-        const u64 d = wave_sum(*sd(c, par, tid));
-        const u64 a = wave_sum(*sa(c, par, tid));
-        const u64 l = wave_or(*sl(c, par, tid));
+        const u64 d = wave_sum(ld(sd(c, par, tid)));
+        const u64 a = wave_sum(ld(sa(c, par, tid)));
+        const u64 l = wave_or(ld(sl(c, par, tid)));
         if (tid == 0) {
             tmp[0] = d;
             tmp[1] = a;
@@ -137,8 +149,8 @@ __device__ __forceinline__ void record(MsCtrl* c, int32_t v, int32_t u, u64 nb, 
     while (nb) {
         const int i = __builtin_ctzll(nb);
         nb &= nb - 1;
-        c->out_lv[i][v] = lvl + 1 - c->start[i];
-        c->out_pa[i][v] = u;
+        ld(&c->out_lv[i])[v] = lvl + 1 - ld(&c->start[i]);
+        ld(&c->out_pa[i])[v] = u;
     }
 }
 
@@ -154,7 +166,7 @@ __device__ __forceinline__ void push_arcs(const MsParams& p, const int64_t (&pos
     for (int i = 0; i < U; ++i) v[i] = ok[i] ? __builtin_nontemporal_load(p.col + pos[i]) : 0;
     u64 t[U];
 #pragma unroll
-    for (int i = 0; i < U; ++i) t[i] = ok[i] ? (f[i] & ~p.vis[v[i]]) : 0ull;
+    for (int i = 0; i < U; ++i) t[i] = ok[i] ? (f[i] & ~p.vis[v[i]]) : 0ull;  // filter only
     u64 old[U];
 #pragma unroll
     for (int i = 0; i < U; ++i) {
@@ -254,24 +266,24 @@ __global__ __launch_bounds__(BLOCK) void k_ms_push(MsParams p, int lvl) {
     __shared__ PushShared<BLOCK> sh;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int64_t G = gridDim.x, bid = blockIdx.x;
-    if (p.ctrl->done) return;
+    if (ld(&p.ctrl->done)) return;
     const LevelView lv = read_level(p.ctrl, lvl);
     if (bid == 0 && tid < 64) {  // statistics of the next level start from zero
         const int np = (lvl + 1) & 1;
-        *sd(p.ctrl, np, tid) = 0;
-        *sa(p.ctrl, np, tid) = 0;
-        *sl(p.ctrl, np, tid) = 0;
+        st(sd(p.ctrl, np, tid), 0ull);
+        st(sa(p.ctrl, np, tid), 0ull);
+        st(sl(p.ctrl, np, tid), 0ull);
     }
     if (lv.disc == 0) {
         if (bid == 0 && tid == 0) {
-            p.ctrl->num_levels = lvl;
-            p.ctrl->done = 1;
+            st(&p.ctrl->num_levels, lvl);
+            st(&p.ctrl->done, 1);
         }
         return;
     }
     if (bid == 0 && tid == 0) {
-        p.ctrl->total_disc += lv.disc;
-        p.ctrl->num_levels = lvl + 1;
+        st(&p.ctrl->total_disc, ld(&p.ctrl->total_disc) + lv.disc);
+        st(&p.ctrl->num_levels, lvl + 1);
     }
     if (!choose_push(p, lv)) return;
     const u64 alive = lv.alive;
@@ -298,7 +310,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_push(MsParams p, int lvl) {
                 if (tid == 0) sh.nactive = 0;
                 __syncthreads();
                 const int h = h0 + tid;
-                if (h < p.num_big && p.big_prefix[h] < s1 && (p.fr[p.big[h]] & alive))
+                if (h < p.num_big && p.big_prefix[h] < s1 && (ld(p.fr + p.big[h]) & alive))
                     sh.active[atomicAdd(&sh.nactive, 1)] = h;
                 __syncthreads();
                 const int na = sh.nactive;
@@ -308,7 +320,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_push(MsParams p, int lvl) {
                     const int64_t a1 = s1 < p.big_prefix[hh + 1] ? s1 : p.big_prefix[hh + 1];
                     const int32_t u = p.big[hh];
                     const int64_t beg = load_off<OffT>(p.off, u) + (a0 - p.big_prefix[hh]);
-                    push_row<kUnroll>(p, beg, a1 - a0, u, p.fr[u] & alive, tid, BLOCK, lvl);
+                    push_row<kUnroll>(p, beg, a1 - a0, u, ld(p.fr + u) & alive, tid, BLOCK, lvl);
                 }
                 __syncthreads();
             }
@@ -326,7 +338,7 @@ __global__ __launch_bounds__(BLOCK) void k_ms_push(MsParams p, int lvl) {
     for (int64_t ti = t0; ti < t1; ++ti) {
         const int64_t v = ti * 64 + lane;
         u64 f = 0;
-        if (v < p.n && !((p.bigmap[v >> 5] >> (v & 31)) & 1u)) f = p.fr[v] & alive;
+        if (v < p.n && !((p.bigmap[v >> 5] >> (v & 31)) & 1u)) f = ld(p.fr + v) & alive;
         const bool has = f != 0;
         const uint64_t m = __ballot(has);
         if (has) {
@@ -359,13 +371,13 @@ __global__ __launch_bounds__(BLOCK) void k_ms_push(MsParams p, int lvl) {
 
 template <typename OffT>
 __global__ __launch_bounds__(256) void k_ms_pull(MsParams p, int lvl) {
-    if (p.ctrl->done) return;
+    if (ld(&p.ctrl->done)) return;
     const LevelView lv = read_level(p.ctrl, lvl);
     if (lv.disc == 0 || choose_push(p, lv)) return;
     const u64 alive = lv.alive;
     const int64_t gsize = (int64_t)gridDim.x * blockDim.x;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < p.n; v += gsize) {
-        const u64 seen = p.vis[v];
+        const u64 seen = ld(p.vis + v);
         const u64 miss = alive & ~seen;
         u64 acc = 0;
         if (miss) {
@@ -377,7 +389,7 @@ __global__ __launch_bounds__(256) void k_ms_pull(MsParams p, int lvl) {
 #pragma unroll
                 for (int q = 0; q < kPullUnroll; ++q) u[q] = j + q < end ? p.col[j + q] : -1;
 #pragma unroll
-                for (int q = 0; q < kPullUnroll; ++q) f[q] = u[q] >= 0 ? p.fr[u[q]] : 0ull;
+                for (int q = 0; q < kPullUnroll; ++q) f[q] = u[q] >= 0 ? ld(p.fr + u[q]) : 0ull;
 #pragma unroll
                 for (int q = 0; q < kPullUnroll; ++q) {
                     const u64 nb = f[q] & miss & ~acc;
@@ -387,20 +399,20 @@ __global__ __launch_bounds__(256) void k_ms_pull(MsParams p, int lvl) {
                         while (b) {
                             const int i = __builtin_ctzll(b);
                             b &= b - 1;
-                            p.ctrl->out_pa[i][v] = u[q];
+                            ld(&p.ctrl->out_pa[i])[v] = u[q];
                         }
                     }
                 }
             }
         }
-        p.nfr[v] = acc;
+        st(p.nfr + v, acc);
         if (acc) {
-            p.vis[v] = seen | acc;
+            st(p.vis + v, seen | acc);
             u64 b = acc;
             while (b) {
                 const int i = __builtin_ctzll(b);
                 b &= b - 1;
-                p.ctrl->out_lv[i][v] = lvl + 1 - p.ctrl->start[i];
+                ld(&p.ctrl->out_lv[i])[v] = lvl + 1 - ld(&p.ctrl->start[i]);
             }
         }
     }
@@ -414,7 +426,7 @@ template <typename OffT, bool kPerSlot>
 __global__ __launch_bounds__(256) void k_ms_finish(MsParams p, int lvl) {
     __shared__ u64 red[4][4];
     __shared__ u64 slot_r[64], slot_a[64];
-    if (p.ctrl->done) return;
+    if (ld(&p.ctrl->done)) return;
     const int tid = threadIdx.x;
     if (kPerSlot) {
         if (tid < 64) {
@@ -426,8 +438,8 @@ __global__ __launch_bounds__(256) void k_ms_finish(MsParams p, int lvl) {
     u64 disc = 0, arcs = 0, alive = 0, work = 0;
     const int64_t gsize = (int64_t)gridDim.x * blockDim.x;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + tid; v < p.n; v += gsize) {
-        const u64 b = p.nfr[v];
-        p.fr[v] = 0;
+        const u64 b = ld(p.nfr + v);
+        st(p.fr + v, 0ull);
         if (b) {
             const int64_t d = load_off<OffT>(p.off, v + 1) - load_off<OffT>(p.off, v);
             const int c = __popcll(b);
@@ -483,9 +495,9 @@ __global__ __launch_bounds__(256) void k_ms_finish(MsParams p, int lvl) {
 __global__ void k_ms_clear(u64* vis, u64* a, u64* b, int64_t n) {
     const int64_t gsize = (int64_t)gridDim.x * blockDim.x;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gsize) {
-        vis[v] = 0;
-        a[v] = 0;
-        b[v] = 0;
+        st(vis + v, 0ull);
+        st(a + v, 0ull);
+        st(b + v, 0ull);
     }
 }
 
@@ -494,45 +506,45 @@ __global__ void k_ms_clear(u64* vis, u64* a, u64* b, int64_t n) {
 template <typename OffT>
 __global__ void k_ms_seed(MsParams p, const int32_t* slots, const int32_t* roots, int32_t count, int lvl) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) p.ctrl->done = 0;
+    if (i == 0) st(&p.ctrl->done, 0);
     if (i >= count) return;
     const int s = slots[i];
     const int32_t r = roots[i];
     const u64 bit = 1ull << s;
     atomicOr(p.vis + r, bit);
     atomicOr(p.fr + r, bit);
-    p.ctrl->out_lv[s][r] = 0;
-    p.ctrl->out_pa[s][r] = r;
+    ld(&p.ctrl->out_lv[s])[r] = 0;
+    ld(&p.ctrl->out_pa[s])[r] = r;
     const int64_t d = load_off<OffT>(p.off, (int64_t)r + 1) - load_off<OffT>(p.off, r);
     const int par = lvl & 1;
     atomicAdd(sd(p.ctrl, par, 0), 1ull);
     atomicAdd(sa(p.ctrl, par, 0), (u64)d);
     atomicOr(sl(p.ctrl, par, 0), bit);
     atomicAdd(sw(p.ctrl, 0), (u64)d);
-    p.ctrl->slot_reached[s] = 1;
-    p.ctrl->slot_arcs[s] = (u64)d;
+    st(&p.ctrl->slot_reached[s], 1ull);
+    st(&p.ctrl->slot_arcs[s], (u64)d);
 }
 
 __global__ void k_ms_summary(MsCtrl* c, int lvl) {
     const int tid = threadIdx.x;
     const int par = lvl & 1;
-    const u64 d = wave_sum(*sd(c, par, tid));
-    const u64 a = wave_sum(*sa(c, par, tid));
-    const u64 l = wave_or(*sl(c, par, tid));
-    const u64 w = wave_sum(*sw(c, tid));
+    const u64 d = wave_sum(ld(sd(c, par, tid)));
+    const u64 a = wave_sum(ld(sa(c, par, tid)));
+    const u64 l = wave_or(ld(sl(c, par, tid)));
+    const u64 w = wave_sum(ld(sw(c, tid)));
     if (tid == 0) {
-        c->sum_disc = d;
-        c->sum_arcs = a;
-        c->sum_alive = l;
-        c->total_arcs = w;
+        st(&c->sum_disc, d);
+        st(&c->sum_arcs, a);
+        st(&c->sum_alive, l);
+        st(&c->total_arcs, w);
     }
 }
 
 __global__ void k_ms_retire(u64* vis, int64_t n, u64 keep) {
     const int64_t gsize = (int64_t)gridDim.x * blockDim.x;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gsize) {
-        const u64 x = vis[v];
-        if (x & ~keep) vis[v] = x & keep;
+        const u64 x = ld(vis + v);
+        if (x & ~keep) st(vis + v, x & keep);
     }
 }
 

@@ -35,6 +35,14 @@
 //              of the next frontier's big rows: one segment per restore block,
 //              placed with a workgroup prefix sum (no atomics).
 // Levels are enqueued in chunks; the host reads a done flag between chunks.
+//
+// Coherence: the eight XCDs have private L2 caches, so a plain load in one
+// launch may return a line that another XCD rewrote in an earlier launch. All
+// state that crosses launches (levels, visited snapshot, frontier, counters,
+// big-row list) is therefore read with device-scope loads, except the per-arc
+// visited probe: it stays a plain load used only as a filter, and a candidate
+// it lets through is confirmed on the level array with a device-scope load
+// before it is claimed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -72,6 +80,18 @@ struct SingleParams {
 };
 
 constexpr int kMinBigShare = 1024;  // fewest big-row arcs handed to one workgroup
+
+// Cross-kernel shared state (bitmaps, level array, lists, counters) is read and
+// written with device-scope accesses: each XCD has its own L2, and a plain load
+// may otherwise hit a line another XCD has since rewritten in an earlier kernel.
+template <typename T>
+__device__ __forceinline__ T ld(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 __device__ __forceinline__ int rank_in(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
@@ -160,10 +180,17 @@ __device__ __forceinline__ void visit_arcs(const SingleParams& p, const int64_t 
             }
         }
     } else {
+        // The plain load above is only a filter: its line may be stale in this
+        // XCD's L2. A candidate is confirmed on the level array, which earlier
+        // kernels wrote and a device-scope load reads exactly: -1 means not
+        // reached in any earlier level.
+        int lv_now[U];
+#pragma unroll
+        for (int i = 0; i < U; ++i) lv_now[i] = (!(w[i] & (1u << (v[i] & 31)))) ? ld(p.levels + v[i]) : 0;
 #pragma unroll
         for (int i = 0; i < U; ++i) {
             const uint32_t b = 1u << (v[i] & 31);
-            if (!(w[i] & b)) {
+            if (!(w[i] & b) && lv_now[i] == -1) {
                 p.vis[v[i] >> 5] = w[i] | b;  // may lose a concurrent update: restored later
                 p.levels[v[i]] = lvl;
                 p.parents[v[i]] = par[i];
@@ -328,14 +355,14 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl) {
     __shared__ ExpandShared<BLOCK> sh;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int64_t G = gridDim.x, bid = blockIdx.x;
-    if (p.ctrl->done) return;
+    if (ld(&p.ctrl->done)) return;
 
     // Termination: the restore pass of the previous level counted this frontier.
     if (tid < 64) {
-        unsigned long long c = *stripe(p.ctrl, lvl & 1, tid);
+        unsigned long long c = ld(stripe(p.ctrl, lvl & 1, tid));
         c = wave_sum(c);
         if (tid == 0) sh.found = c;
-        if (bid == 0) *stripe(p.ctrl, (lvl + 1) & 1, tid) = 0;  // counters for the next level
+        if (bid == 0) st(stripe(p.ctrl, (lvl + 1) & 1, tid), 0ull);  // counters for the next level
     }
     __syncthreads();
     if (sh.found == 0) {
@@ -349,10 +376,10 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl) {
 
     // ---- rows of degree > T2: the level's big-row arcs, split evenly
     if (tid < 64) {
-        unsigned long long c = p.ctrl->bigarcs[lvl & 1][tid * kStripeStride];
+        unsigned long long c = ld(&p.ctrl->bigarcs[lvl & 1][tid * kStripeStride]);
         c = wave_sum(c);
         if (tid == 0) sh.big_total = c;
-        if (bid == 0) p.ctrl->bigarcs[(lvl + 1) & 1][tid * kStripeStride] = 0;
+        if (bid == 0) st(&p.ctrl->bigarcs[(lvl + 1) & 1][tid * kStripeStride], 0ull);
     }
     __syncthreads();
     const int64_t ta = (int64_t)sh.big_total;
@@ -370,7 +397,7 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl) {
 #pragma unroll
             for (int k = 0; k < PER_T; ++k) {
                 const int i = tid * PER_T + k;
-                vals[k] = i < R ? p.seg_arcs[i] : 0u;
+                vals[k] = i < R ? ld(p.seg_arcs + i) : 0u;
                 mine += vals[k];
             }
             uint32_t excl;
@@ -398,10 +425,10 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl) {
                 seg = lo;
                 const int64_t local = a0 - (int64_t)sh.segpre[seg];
                 const int first = p.seg_start[seg];
-                int l2 = 0, h2 = (int)p.seg_cnt[seg] - 1;  // last row with offset <= local
+                int l2 = 0, h2 = (int)ld(p.seg_cnt + seg) - 1;  // last row with offset <= local
                 while (l2 < h2) {
                     const int mid = (l2 + h2 + 1) >> 1;
-                    if ((int64_t)p.bl_pre[first + mid] <= local)
+                    if ((int64_t)ld(p.bl_pre + first + mid) <= local)
                         l2 = mid;
                     else
                         h2 = mid - 1;
@@ -411,7 +438,7 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl) {
             int64_t pos = a0;
             while (pos < a1) {
                 if (tid == 0) {
-                    while (seg < R && idx >= (int)p.seg_cnt[seg]) {  // next non-empty segment
+                    while (seg < R && idx >= (int)ld(p.seg_cnt + seg)) {  // next non-empty segment
                         ++seg;
                         idx = 0;
                     }
@@ -419,8 +446,8 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl) {
                 if (tid == 0 && seg >= R) sh.row_len = 0;  // list exhausted (cannot happen: a1 <= total)
                 if (tid == 0 && seg < R) {
                     const int slot = p.seg_start[seg] + idx;
-                    const int32_t u = p.bl_u[slot];
-                    const int64_t row_start = (int64_t)sh.segpre[seg] + p.bl_pre[slot];
+                    const int32_t u = ld(p.bl_u + slot);
+                    const int64_t row_start = (int64_t)sh.segpre[seg] + ld(p.bl_pre + slot);
                     const int64_t beg = load_off<OffT>(p.off, u);
                     const int64_t deg = load_off<OffT>(p.off, (int64_t)u + 1) - beg;
                     const int64_t end = row_start + deg < a1 ? row_start + deg : a1;
@@ -449,7 +476,7 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl) {
     uint32_t head = 0, tail = 0;
     for (int64_t base = w0; base < w1; base += 64) {
         const int64_t wi = base + lane;
-        uint32_t word = wi < w1 ? (p.fr[wi] & ~p.bigmap[wi]) : 0u;
+        uint32_t word = wi < w1 ? (ld(p.fr + wi) & ~p.bigmap[wi]) : 0u;
         while (true) {
             const bool has = word != 0;
             const uint64_t m = __ballot(has);
@@ -493,7 +520,7 @@ __global__ __launch_bounds__(kRestoreBlock) void k_restore(SingleParams p, int l
     constexpr int BLOCK = kRestoreBlock;
     __shared__ unsigned long long red[BLOCK / 64];
     __shared__ uint32_t tmp[BLOCK / 64];
-    if (p.ctrl->done) return;
+    if (ld(&p.ctrl->done)) return;
     const int tid = threadIdx.x;
     const int64_t G = gridDim.x, bid = blockIdx.x;
     const int next = lvl + 1;
@@ -502,38 +529,48 @@ __global__ __launch_bounds__(kRestoreBlock) void k_restore(SingleParams p, int l
     const int32_t first = p.seg_start[bid];
     for (int64_t c = bid; c * BLOCK < p.words; c += G) {
         const int64_t w = c * BLOCK + tid;
-        uint32_t exact = 0;
+        const int lane = tid & 63;
+        uint32_t cur = 0, prev = 0, exact = 0;
         if (w < p.words) {
-            const uint32_t cur = p.vis[w];
-            const uint32_t prev = p.vis_prev[w];
-            if (cur != prev) {
-                if (kAtomic) {
-                    exact = cur & ~prev;
-                } else {
-                    // A racing read-modify-write may have dropped bits of this
-                    // level, never added foreign ones, and always leaves one of
-                    // its bits: the level array says exactly who was discovered.
-                    const int64_t v0 = w * 32;
-                    if (v0 + 32 <= p.n && (reinterpret_cast<uintptr_t>(p.levels) & 15) == 0) {
-                        const int4* l4 = reinterpret_cast<const int4*>(p.levels + v0);
-#pragma unroll
-                        for (int q = 0; q < 8; ++q) {
-                            const int4 x = l4[q];
-                            exact |= (uint32_t)(x.x == next) << (4 * q);
-                            exact |= (uint32_t)(x.y == next) << (4 * q + 1);
-                            exact |= (uint32_t)(x.z == next) << (4 * q + 2);
-                            exact |= (uint32_t)(x.w == next) << (4 * q + 3);
-                        }
-                    } else {
-                        for (int b = 0; b < 32 && v0 + b < p.n; ++b)
-                            exact |= (uint32_t)(p.levels[v0 + b] == next) << b;
-                    }
+            cur = ld(p.vis + w);
+            prev = ld(p.vis_prev + w);
+        }
+        const bool touched = w < p.words && cur != prev;
+        if (kAtomic) {
+            exact = touched ? (cur & ~prev) : 0u;
+        } else {
+            // A racing read-modify-write may have dropped bits (of this level,
+            // or of earlier ones through a stale filter read; the snapshot
+            // puts those back), never added foreign ones, and always leaves
+            // one of its bits set: the level array says exactly who was
+            // discovered. Two touched words per step: each half-wave reads
+            // one word's 32 levels.
+            uint64_t tm = __ballot(touched);
+            const int64_t wave_w0 = c * BLOCK + (tid & ~63);
+            while (tm) {
+                const int wa = __builtin_ctzll(tm);
+                tm &= tm - 1;
+                int wb = -1;
+                if (tm) {
+                    wb = __builtin_ctzll(tm);
+                    tm &= tm - 1;
                 }
-                const uint32_t nv = prev | exact;
-                if (cur != nv) p.vis[w] = nv;
-                p.vis_prev[w] = nv;
+                const int src = lane < 32 ? wa : wb;
+                const int64_t v = (wave_w0 + src) * 32 + (lane & 31);
+                const bool okl = src >= 0 && v < p.n;
+                const int lvv = okl ? ld(p.levels + v) : -1;
+                const uint64_t m = __ballot(lvv == next);
+                if (lane == wa) exact = (uint32_t)m;
+                if (lane == wb) exact = (uint32_t)(m >> 32);
             }
-            p.fr[w] = exact;
+        }
+        if (touched) {
+            const uint32_t nv = prev | exact;
+            if (cur != nv) st(p.vis + w, nv);
+            st(p.vis_prev + w, nv);
+        }
+        if (w < p.words) {
+            st(p.fr + w, exact);
             found += (unsigned long long)__popc(exact);
         }
         // Append the next frontier's big rows of this chunk to the segment.
@@ -551,8 +588,8 @@ __global__ __launch_bounds__(kRestoreBlock) void k_restore(SingleParams p, int l
             uint32_t at = seg_a + arc_excl;
             for (uint32_t x = big; x; x &= x - 1) {
                 const int64_t u = w * 32 + __builtin_ctz(x);
-                p.bl_u[slot] = (int32_t)u;
-                p.bl_pre[slot] = at;
+                st(p.bl_u + slot, (int32_t)u);
+                st(p.bl_pre + slot, at);
                 at += (uint32_t)(load_off<OffT>(p.off, u + 1) - load_off<OffT>(p.off, u));
                 ++slot;
             }
@@ -570,8 +607,8 @@ __global__ __launch_bounds__(kRestoreBlock) void k_restore(SingleParams p, int l
             atomicAdd(stripe(p.ctrl, next & 1, (int)(bid % kStripes)), a);
             p.reached_slot[bid] += a;
         }
-        p.seg_cnt[bid] = seg_n;
-        p.seg_arcs[bid] = seg_a;
+        st(p.seg_cnt + bid, seg_n);
+        st(p.seg_arcs + bid, seg_a);
         if (seg_a) atomicAdd(&p.ctrl->bigarcs[next & 1][(bid % kStripes) * kStripeStride], (unsigned long long)seg_a);
     }
 }

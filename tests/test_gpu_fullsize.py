@@ -1,0 +1,69 @@
+"""Parity at the full workload sizes, in the launch configuration the benchmark
+times: R-MAT scale 24 and 26 single-root (oracle on sampled roots, the V2-V5
+certificate on more), the batched configurations (R-MAT scale 22 with 64 roots,
+Erdos-Renyi 2^22 with average degree 16 in batches of 8/32/64)."""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+import paper_1604_02844_amd as bfs
+from tests.gpu_helpers import check_root, gpu_run, load, torch_mod
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+def certify_row(g, root, lv, pa):
+    code, bad = oracle.certify(g.offsets, g.cols, int(root), lv, pa)
+    assert code == 0, f"{g.name} root {root}: {oracle.CHECK_NAMES[code]} at {bad}"
+
+
+@pytest.mark.parametrize("scale,oracle_roots,cert_roots", [(24, 2, 4), (26, 1, 1)])
+def test_single_root_full_scale(scale, oracle_roots, cert_roots):
+    torch_mod()
+    print(f"[case] generating R-MAT scale {scale}", flush=True)
+    g = graphgen.cached("rmat", scale=scale, edgefactor=16, seed=1)
+    dg = load(g)
+    roots = graphgen.pick_roots(g, 64, seed=2)
+    for r in roots[:oracle_roots]:
+        check_root(g, dg, int(r))
+    for r in roots[oracle_roots:oracle_roots + cert_roots]:
+        print(f"[case] certify scale {scale} root {r}", flush=True)
+        lv, pa, st = gpu_run(dg, int(r))
+        certify_row(g, r, lv, pa)
+        assert st["reached"] == int((lv >= 0).sum())
+
+
+def test_batch_rmat22_64_roots():
+    torch = torch_mod()
+    g = graphgen.cached("rmat", scale=22, edgefactor=16, seed=1)
+    dg = load(g)
+    roots = graphgen.pick_roots(g, 64, seed=2)
+    lv = torch.empty((64, g.n), dtype=torch.int32, device="cuda")
+    pa = torch.empty((64, g.n), dtype=torch.int32, device="cuda")
+    print("[case] bfs_run_batch R-MAT 22, 64 roots", flush=True)
+    st = bfs.bfs_run_batch(dg, roots, lv, pa)
+    L, P = lv.cpu().numpy(), pa.cpu().numpy()
+    for i in (0, 31, 63):
+        ref, _, _ = oracle.bfs(g.offsets, g.cols, int(roots[i]))
+        assert oracle.validate(g.offsets, g.cols, int(roots[i]), ref, L[i], P[i])[0] == 0
+    for i, r in enumerate(roots):
+        certify_row(g, r, L[i], P[i])
+    assert st["reached"] == int((L >= 0).sum())
+
+
+def test_batch_er22_widths():
+    torch = torch_mod()
+    g = graphgen.cached("er", n=1 << 22, avg_degree=16, seed=1)
+    dg = load(g)
+    pool = graphgen.pick_roots(g, 64, seed=2)
+    for b in (8, 32, 64):
+        lv = torch.empty((b, g.n), dtype=torch.int32, device="cuda")
+        pa = torch.empty((b, g.n), dtype=torch.int32, device="cuda")
+        print(f"[case] bfs_run_batch ER 2^22 d16, {b} roots", flush=True)
+        bfs.bfs_run_batch(dg, pool[:b], lv, pa)
+        L, P = lv.cpu().numpy(), pa.cpu().numpy()
+        ref, _, _ = oracle.bfs(g.offsets, g.cols, int(pool[0]))
+        assert oracle.validate(g.offsets, g.cols, int(pool[0]), ref, L[0], P[0])[0] == 0
+        for i in range(0, b, max(1, b // 8)):
+            certify_row(g, pool[i], L[i], P[i])

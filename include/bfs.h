@@ -85,16 +85,20 @@ typedef struct {
 /* Kernel tunables. Zero fields mean "library default". See bfs_autotune. */
 typedef struct {
     int32_t small_max_degree;   /* T1: rows with d <= T1 are packed, several per wavefront */
-    int32_t wave_max_degree;    /* T2: T1 < d <= T2 gets one wavefront; rows with d > T2 are
-                                   cut into chunks of chunk_arcs arcs, one workgroup each */
-    int32_t chunk_arcs;         /* arcs per workgroup chunk of a row above T2 */
+    int32_t wave_max_degree;    /* T2: T1 < d <= T2 gets one wavefront; the arcs of all rows
+                                   with d > T2 are split evenly over the whole grid */
+    int32_t chunk_arcs;         /* fewest arcs of rows above T2 handed to one workgroup */
     int32_t blocks_per_cu;      /* workgroups per compute unit of the expansion grid */
-    int32_t block_size;         /* threads per workgroup: 256 or 512 */
+    int32_t block_size;         /* threads per expansion workgroup: 256, 512 or 1024 */
     int32_t batch_width;        /* bfs_run_batch: roots per bit-sliced pass (1..64) */
     int32_t update_mode;        /* bitmap update: 1 = plain read-modify-write followed by the
                                    restoration pass (the paper's atomic-free scheme, section
                                    3.3.2), 2 = atomicOr claim; 0 = library default */
-    int32_t reserved;
+    int32_t hot_vertices;       /* single-root runs: every workgroup keeps the visited bits of
+                                   this many vertices (the highest-degree ones, taken from a
+                                   degree-ordered copy of the graph) in LDS during levels with
+                                   large frontiers and probes them there first; rounded up to
+                                   a multiple of 2048; -1 = off, 0 = library default */
 } bfs_tunables;
 
 /* ---- graph residency ------------------------------------------------------ */
@@ -102,7 +106,7 @@ typedef struct {
 /*
  * Make a CSR graph resident on the current HIP device.
  *   n        number of vertices, 1 <= n <= 2^31-1.
- *   nnz      number of arcs (directed CSR entries), >= 0.
+ *   nnz      number of arcs (directed CSR entries), 0 <= nnz <= 2^32 - 1.
  *   offsets  int64_t[n+1] (int32_t[n+1] with BFS_LOAD_OFFSETS_I32): row v is
  *            cols[offsets[v] .. offsets[v+1]). offsets[0]==0, offsets[n]==nnz,
  *            non-decreasing.

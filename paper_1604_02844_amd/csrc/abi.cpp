@@ -125,19 +125,7 @@ int bfs_graph_set_tunables(bfs_graph* g, const bfs_tunables* t) {
     return guarded([&] {
         if (!g || !t) bfs::fail(BFS_E_INVALID_ARG, "NULL argument");
         DeviceScope ds(g->device);
-        bfs_tunables r = bfs::resolve_tunables(g, *t);
-        // The big-row table is shared by every run on the graph: rebuild it
-        // only after in-flight work has drained.
-        if (r.wave_max_degree != g->big_threshold) {
-            bfs::hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
-            std::lock_guard<std::mutex> lk(g->mu);
-            bfs::rebuild_big(g, r.wave_max_degree);
-            // Workspaces hold lists sized for the old table: drop them.
-            for (auto* w : g->ws_all) g->device_bytes -= w->bytes;
-            for (auto* w : g->ms_all) g->device_bytes -= w->bytes;
-            bfs::free_workspaces(g);
-        }
-        g->tun = r;
+        bfs::apply_tunables(g, bfs::resolve_tunables(g, *t));
         return BFS_OK;
     });
 }

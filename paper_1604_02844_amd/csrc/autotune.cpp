@@ -28,19 +28,8 @@ struct DevBuf {
     ~DevBuf() { (void)hipFree(p); }
 };
 
-// Apply tunables to the graph (rebuilding the big-row table when T2 moves).
-void apply(bfs_graph* g, const bfs_tunables& t) {
-    const bfs_tunables r = resolve_tunables(g, t);
-    if (r.wave_max_degree != g->big_threshold) {
-        hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
-        std::lock_guard<std::mutex> lk(g->mu);
-        rebuild_big(g, r.wave_max_degree);
-        for (auto* w : g->ws_all) g->device_bytes -= w->bytes;
-        for (auto* w : g->ms_all) g->device_bytes -= w->bytes;
-        free_workspaces(g);
-    }
-    g->tun = r;
-}
+// Apply tunables to the graph (rebuilding derived tables when needed).
+void apply(bfs_graph* g, const bfs_tunables& t) { apply_tunables(g, resolve_tunables(g, t)); }
 
 // Time one candidate; fills `levels` (n per root, host) when not null.
 double time_single(bfs_graph* g, const int32_t* roots, int count, hipStream_t s, int32_t* lv, int32_t* pa,
@@ -140,10 +129,11 @@ void autotune(bfs_graph* g, const int32_t* roots, int32_t num_roots, int32_t mod
     };
     std::vector<Axis> axes;
     if (mode == 0) {
-        axes = {{&bfs_tunables::update_mode, {1, 2}},
+        axes = {{&bfs_tunables::hot_vertices, {-1, 1 << 17, 1 << 19}},
+                {&bfs_tunables::block_size, {256, 512, 1024}},
+                {&bfs_tunables::update_mode, {1, 2}},
                 {&bfs_tunables::wave_max_degree, {64, 128, 256, 512, 1024}},
-                {&bfs_tunables::small_max_degree, {8, 16, 32, 64}},
-                {&bfs_tunables::block_size, {256, 512}},
+                {&bfs_tunables::small_max_degree, {8, 16, 32, 64, 256}},
                 {&bfs_tunables::blocks_per_cu, {0, 2, 4}}};
     } else {
         axes = {{&bfs_tunables::batch_width, {16, 32, 64}},

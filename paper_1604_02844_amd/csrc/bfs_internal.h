@@ -5,6 +5,7 @@
 
 #include <atomic>
 #include <cstdint>
+#include <memory>
 #include <mutex>
 #include <stdexcept>
 #include <string>
@@ -60,6 +61,9 @@ struct Workspace {
     uint32_t* seg_cnt = nullptr;
     uint32_t* seg_arcs = nullptr;
     int32_t big_capacity = 0;
+    uint32_t* hot_vis = nullptr;    // compact visited bitmap of the hot vertices (ids 32r)
+    int32_t hot_capacity = 0;       // its words
+    int32_t* lv_new = nullptr;      // levels in the degree-ordered ids (runs on the copy)
     Ctrl* host_ctrl = nullptr;      // pinned mirror for stats
     int32_t* out_levels = nullptr;  // staging for BFS_OUT_HOST
     int32_t* out_parents = nullptr;
@@ -106,6 +110,36 @@ struct MsWorkspace {
     int64_t bytes = 0;
 };
 
+// Rows with degree above a threshold, for one vertex order: their ids, the
+// exclusive prefix of their degrees, a bitmap that removes them from the
+// per-wavefront frontier scan, and the capacity of each restore block's
+// segment of the per-level big-row list.
+struct BigTable {
+    int32_t threshold = 0;
+    int32_t num_big = 0;
+    int64_t big_arcs = 0;
+    int32_t* d_big = nullptr;
+    int64_t* d_big_prefix = nullptr;
+    uint32_t* d_bigmap = nullptr;
+    int32_t* d_seg_start = nullptr;
+    int64_t bytes = 0;
+};
+
+// Degree-ordered copy of the graph for single-root runs. The `hot` vertices of
+// highest degree take ids 32r (r < hot): bit 0 of visited word r, so their
+// visited bits form a compact bitmap that fits in LDS. Every other vertex keeps
+// its relative order, so frontier words stay as evenly loaded as in the
+// caller's order. Offsets are int64; outputs are written at caller ids.
+struct HotLayout {
+    int32_t hot = 0;
+    int64_t* d_off = nullptr;       // [n+1], new order
+    int32_t* d_col = nullptr;       // [nnz], new ids
+    int32_t* d_new2old = nullptr;   // [n]
+    std::vector<int32_t> old2new;   // host copy, for the root
+    BigTable big;
+    int64_t bytes = 0;
+};
+
 }  // namespace bfs
 
 struct bfs_graph {
@@ -118,17 +152,12 @@ struct bfs_graph {
     int64_t max_degree = 0;
     int cu_count = 0;
 
-    // Rows with degree > big_threshold are split over the whole grid: their
-    // ids, the exclusive prefix sum of their degrees, and a bitmap marking them.
-    int32_t big_threshold = 0;
-    int32_t num_big = 0;
-    int64_t big_arcs = 0;
-    int32_t* d_big = nullptr;
-    int64_t* d_big_prefix = nullptr;
-    uint32_t* d_bigmap = nullptr;
-    // Restore grid and where each restore block's big-row segment starts.
+    // Rows above T2 in the caller's order (split over the whole grid).
+    bfs::BigTable big;
+    // Restore grid (one big-row list segment per restore block).
     int32_t restore_grid = 0;
-    int32_t* d_seg_start = nullptr;
+    // Degree-ordered copy for single-root runs with an LDS hot bitmap.
+    std::unique_ptr<bfs::HotLayout> hot;
 
     bfs_tunables tun{};
     std::mutex mu;
@@ -144,10 +173,28 @@ namespace bfs {
 
 bfs_tunables default_tunables(const bfs_graph* g);
 bfs_tunables resolve_tunables(const bfs_graph* g, const bfs_tunables& t);
-void rebuild_big(bfs_graph* g, int32_t threshold);
+// Make the graph's derived tables match resolved tunables `r` (big-row tables
+// of both orders, the degree-ordered copy) and store them. Waits for in-flight
+// work first when anything has to be rebuilt. Caller must not hold g->mu.
+void apply_tunables(bfs_graph* g, const bfs_tunables& r);
+void build_big_table(bfs::BigTable& t, const void* d_off, bool off32, int64_t n, int32_t threshold, int restore_grid,
+                     int cu_count, int64_t* max_degree);
+void free_big_table(bfs::BigTable& t);
+// Hot vertices used for these tunables (0 = no degree-ordered copy).
+int32_t hot_count(const bfs_graph* g, const bfs_tunables& t);
+void build_hot_layout(bfs_graph* g, int32_t hot, int32_t threshold);
+void free_hot_layout(bfs_graph* g);
+// Device part of the copy (single.hip): new columns of every new row.
+void launch_relabel_cols(const bfs_graph* g, const int64_t* d_noff, const int32_t* d_new2old,
+                         const int32_t* d_old2new, int32_t* d_ncol);
 int64_t padded_words(int64_t n);
 // Blocks of the restore pass: 256-word chunks, chunk c handled by block c % grid.
 constexpr int kRestoreBlock = 256;
+// Upper bound of the restore grid (= number of big-row list segments); the
+// expansion kernel keeps two prefix arrays of this length in LDS.
+constexpr int kMaxRestoreGrid = 1024;
+// Largest LDS snapshot of hot visited words per expansion workgroup (128 KiB).
+constexpr int kMaxHotWords = 32768;
 int restore_grid_for(int64_t words, int cu_count);
 
 Workspace* acquire_ws(bfs_graph* g, hipStream_t s);

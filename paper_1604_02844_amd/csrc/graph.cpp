@@ -55,66 +55,212 @@ int64_t padded_words(int64_t n) {
 
 int restore_grid_for(int64_t words, int cu_count) {
     const int64_t chunks = (words + kRestoreBlock - 1) / kRestoreBlock;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(chunks, (int64_t)std::max(cu_count, 1) * 8));
+    const int64_t cap = std::min<int64_t>((int64_t)std::max(cu_count, 1) * 4, kMaxRestoreGrid);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(chunks, cap));
 }
 
-// Table of rows with degree > threshold (split over the whole expansion grid)
-// and the bitmap that removes them from the per-wavefront frontier scan.
-void rebuild_big(bfs_graph* g, int32_t threshold) {
-    if (threshold < 1) threshold = 1;
-    if (g->d_big && g->big_threshold == threshold) return;
-    if (g->d_big) BFS_HIP(hipFree(g->d_big));
-    if (g->d_big_prefix) BFS_HIP(hipFree(g->d_big_prefix));
-    if (g->d_bigmap) BFS_HIP(hipFree(g->d_bigmap));
-    if (g->d_seg_start) BFS_HIP(hipFree(g->d_seg_start));
-    g->d_big = nullptr;
-    g->d_big_prefix = nullptr;
-    g->d_bigmap = nullptr;
-    g->d_seg_start = nullptr;
-    g->big_threshold = threshold;
-    g->num_big = 0;
-    g->big_arcs = 0;
-    std::vector<int64_t> off((size_t)g->n + 1);
-    if (g->off32) {
-        std::vector<int32_t> o32((size_t)g->n + 1);
-        BFS_HIP(hipMemcpy(o32.data(), g->d_off, o32.size() * 4, hipMemcpyDeviceToHost));
+namespace {
+
+std::vector<int64_t> host_offsets(const void* d_off, bool off32, int64_t n) {
+    std::vector<int64_t> off((size_t)n + 1);
+    if (off32) {
+        std::vector<int32_t> o32((size_t)n + 1);
+        BFS_HIP(hipMemcpy(o32.data(), d_off, o32.size() * 4, hipMemcpyDeviceToHost));
         for (size_t i = 0; i < o32.size(); ++i) off[i] = o32[i];
     } else {
-        BFS_HIP(hipMemcpy(off.data(), g->d_off, off.size() * 8, hipMemcpyDeviceToHost));
+        BFS_HIP(hipMemcpy(off.data(), d_off, off.size() * 8, hipMemcpyDeviceToHost));
     }
-    const int64_t words = padded_words(g->n);
+    return off;
+}
+
+}  // namespace
+
+void free_big_table(BigTable& t) {
+    if (t.d_big) (void)hipFree(t.d_big);
+    if (t.d_big_prefix) (void)hipFree(t.d_big_prefix);
+    if (t.d_bigmap) (void)hipFree(t.d_bigmap);
+    if (t.d_seg_start) (void)hipFree(t.d_seg_start);
+    t = BigTable{};
+}
+
+// Rows with degree > threshold (split over the whole expansion grid) and the
+// bitmap that removes them from the per-wavefront frontier scan.
+void build_big_table(BigTable& t, const void* d_off, bool off32, int64_t n, int32_t threshold, int restore_grid,
+                     int cu_count, int64_t* max_degree) {
+    (void)cu_count;
+    if (threshold < 1) threshold = 1;
+    free_big_table(t);
+    t.threshold = threshold;
+    const std::vector<int64_t> off = host_offsets(d_off, off32, n);
+    const int64_t words = padded_words(n);
     std::vector<uint32_t> bigmap((size_t)words, 0u);
     std::vector<int32_t> big;
     std::vector<int64_t> prefix(1, 0);
-    g->max_degree = 0;
-    for (int64_t v = 0; v < g->n; ++v) {
+    int64_t maxd = 0;
+    for (int64_t v = 0; v < n; ++v) {
         const int64_t d = off[(size_t)v + 1] - off[(size_t)v];
-        g->max_degree = std::max(g->max_degree, d);
+        maxd = std::max(maxd, d);
         if (d > threshold) {
             big.push_back((int32_t)v);
             prefix.push_back(prefix.back() + d);
             bigmap[(size_t)(v >> 5)] |= 1u << (v & 31);
         }
     }
-    g->num_big = (int32_t)big.size();
-    g->big_arcs = prefix.back();
-    BFS_HIP(hipMalloc(&g->d_big, std::max<size_t>(big.size(), 1) * 4));
-    BFS_HIP(hipMalloc(&g->d_big_prefix, prefix.size() * 8));
-    BFS_HIP(hipMalloc(&g->d_bigmap, (size_t)words * 4));
-    if (!big.empty()) BFS_HIP(hipMemcpy(g->d_big, big.data(), big.size() * 4, hipMemcpyHostToDevice));
-    BFS_HIP(hipMemcpy(g->d_big_prefix, prefix.data(), prefix.size() * 8, hipMemcpyHostToDevice));
-    BFS_HIP(hipMemcpy(g->d_bigmap, bigmap.data(), (size_t)words * 4, hipMemcpyHostToDevice));
-    // Segment capacities of the restore pass: the big rows inside the chunks
-    // that each restore block visits.
-    g->restore_grid = restore_grid_for(words, g->cu_count);
-    std::vector<int32_t> seg((size_t)g->restore_grid + 1, 0);
-    for (int64_t w = 0; w < words; ++w) {
-        const int b = (int)((w / kRestoreBlock) % g->restore_grid);
-        seg[(size_t)b + 1] += __builtin_popcount(bigmap[(size_t)w]);
+    if (max_degree) *max_degree = maxd;
+    t.num_big = (int32_t)big.size();
+    t.big_arcs = prefix.back();
+    try {
+        BFS_HIP(hipMalloc(&t.d_big, std::max<size_t>(big.size(), 1) * 4));
+        BFS_HIP(hipMalloc(&t.d_big_prefix, prefix.size() * 8));
+        BFS_HIP(hipMalloc(&t.d_bigmap, (size_t)words * 4));
+        if (!big.empty()) BFS_HIP(hipMemcpy(t.d_big, big.data(), big.size() * 4, hipMemcpyHostToDevice));
+        BFS_HIP(hipMemcpy(t.d_big_prefix, prefix.data(), prefix.size() * 8, hipMemcpyHostToDevice));
+        BFS_HIP(hipMemcpy(t.d_bigmap, bigmap.data(), (size_t)words * 4, hipMemcpyHostToDevice));
+        // Segment capacities of the restore pass: the big rows inside the
+        // chunks that each restore block visits.
+        std::vector<int32_t> seg((size_t)restore_grid + 1, 0);
+        for (int64_t w = 0; w < words; ++w) {
+            const int b = (int)((w / kRestoreBlock) % restore_grid);
+            seg[(size_t)b + 1] += __builtin_popcount(bigmap[(size_t)w]);
+        }
+        for (int b = 0; b < restore_grid; ++b) seg[(size_t)b + 1] += seg[(size_t)b];
+        BFS_HIP(hipMalloc(&t.d_seg_start, seg.size() * 4));
+        BFS_HIP(hipMemcpy(t.d_seg_start, seg.data(), seg.size() * 4, hipMemcpyHostToDevice));
+        t.bytes = (int64_t)std::max<size_t>(big.size(), 1) * 4 + (int64_t)prefix.size() * 8 + words * 4 +
+                  (int64_t)seg.size() * 4;
+    } catch (...) {
+        free_big_table(t);
+        throw;
     }
-    for (int b = 0; b < g->restore_grid; ++b) seg[(size_t)b + 1] += seg[(size_t)b];
-    BFS_HIP(hipMalloc(&g->d_seg_start, seg.size() * 4));
-    BFS_HIP(hipMemcpy(g->d_seg_start, seg.data(), seg.size() * 4, hipMemcpyHostToDevice));
+}
+
+int32_t hot_count(const bfs_graph* g, const bfs_tunables& t) {
+    if (t.hot_vertices <= 0) return 0;
+    int64_t h = ((int64_t)t.hot_vertices + 2047) / 2048 * 2048;  // whole 64-bit words of the compact bitmap
+    h = std::min<int64_t>(h, (int64_t)kMaxHotWords * 32);
+    h = std::min<int64_t>(h, (g->n + 31) / 32);                   // ids 32r must exist
+    return (int32_t)std::max<int64_t>(h, 0);
+}
+
+void free_hot_layout(bfs_graph* g) {
+    if (!g->hot) return;
+    HotLayout& h = *g->hot;
+    if (h.d_off) (void)hipFree(h.d_off);
+    if (h.d_col) (void)hipFree(h.d_col);
+    if (h.d_new2old) (void)hipFree(h.d_new2old);
+    free_big_table(h.big);
+    g->device_bytes -= h.bytes;
+    g->hot.reset();
+}
+
+// The degree-ordered copy. Hot vertices: the `hot` highest degrees (ties to
+// the lower id), placed at ids 32r in increasing caller-id order; all other
+// vertices fill the remaining ids in increasing caller-id order. Rows keep
+// their arc order; columns are renamed on the device.
+void build_hot_layout(bfs_graph* g, int32_t hot, int32_t threshold) {
+    free_hot_layout(g);
+    if (hot <= 0) return;
+    const int64_t n = g->n;
+    const std::vector<int64_t> off = host_offsets(g->d_off, g->off32, n);
+    // Degree threshold D with #(deg > D) < hot <= #(deg >= D), by a histogram.
+    int64_t maxd = 0;
+    for (int64_t v = 0; v < n; ++v) maxd = std::max(maxd, off[(size_t)v + 1] - off[(size_t)v]);
+    std::vector<int64_t> cnt((size_t)maxd + 2, 0);
+    for (int64_t v = 0; v < n; ++v) ++cnt[(size_t)(off[(size_t)v + 1] - off[(size_t)v])];
+    int64_t D = maxd, above = 0;
+    while (D > 0 && above + cnt[(size_t)D] < hot) above += cnt[(size_t)D--];
+    int64_t take_eq = hot - above;  // vertices of degree exactly D still needed
+    std::vector<char> is_hot((size_t)n, 0);
+    std::vector<int32_t> hot_ids;
+    hot_ids.reserve((size_t)hot);
+    for (int64_t v = 0; v < n && (int64_t)hot_ids.size() < hot; ++v) {
+        const int64_t d = off[(size_t)v + 1] - off[(size_t)v];
+        if (d > D || (d == D && take_eq > 0)) {
+            if (d == D) --take_eq;
+            is_hot[(size_t)v] = 1;
+            hot_ids.push_back((int32_t)v);
+        }
+    }
+    if ((int64_t)hot_ids.size() != hot) fail(BFS_E_INTERNAL, "hot vertex selection");
+    std::vector<int32_t> new2old((size_t)n), old2new((size_t)n);
+    int64_t cold = 0;
+    for (int64_t x = 0; x < n; ++x) {
+        if ((x & 31) == 0 && (x >> 5) < hot) {
+            new2old[(size_t)x] = hot_ids[(size_t)(x >> 5)];
+        } else {
+            while (is_hot[(size_t)cold]) ++cold;
+            new2old[(size_t)x] = (int32_t)cold++;
+        }
+        old2new[(size_t)new2old[(size_t)x]] = (int32_t)x;
+    }
+    std::vector<int64_t> noff((size_t)n + 1, 0);
+    for (int64_t x = 0; x < n; ++x) {
+        const int64_t u = new2old[(size_t)x];
+        noff[(size_t)x + 1] = noff[(size_t)x] + (off[(size_t)u + 1] - off[(size_t)u]);
+    }
+    auto h = std::make_unique<HotLayout>();
+    h->hot = hot;
+    int32_t* d_old2new = nullptr;
+    try {
+        BFS_HIP(hipMalloc(&h->d_off, noff.size() * 8));
+        BFS_HIP(hipMalloc(&h->d_col, std::max<size_t>((size_t)g->nnz * 4, 4)));
+        BFS_HIP(hipMalloc(&h->d_new2old, (size_t)n * 4));
+        BFS_HIP(hipMalloc(&d_old2new, (size_t)n * 4));
+        BFS_HIP(hipMemcpy(h->d_off, noff.data(), noff.size() * 8, hipMemcpyHostToDevice));
+        BFS_HIP(hipMemcpy(h->d_new2old, new2old.data(), (size_t)n * 4, hipMemcpyHostToDevice));
+        BFS_HIP(hipMemcpy(d_old2new, old2new.data(), (size_t)n * 4, hipMemcpyHostToDevice));
+        launch_relabel_cols(g, h->d_off, h->d_new2old, d_old2new, h->d_col);
+        BFS_HIP(hipDeviceSynchronize());
+        BFS_HIP(hipFree(d_old2new));
+        d_old2new = nullptr;
+        build_big_table(h->big, h->d_off, false, n, threshold, g->restore_grid, g->cu_count, nullptr);
+        if (h->big.num_big != g->big.num_big) fail(BFS_E_INTERNAL, "degree-ordered copy changed the big rows");
+    } catch (...) {
+        if (d_old2new) (void)hipFree(d_old2new);
+        if (h->d_off) (void)hipFree(h->d_off);
+        if (h->d_col) (void)hipFree(h->d_col);
+        if (h->d_new2old) (void)hipFree(h->d_new2old);
+        free_big_table(h->big);
+        throw;
+    }
+    h->old2new = std::move(old2new);
+    h->bytes = (int64_t)noff.size() * 8 + g->nnz * 4 + n * 4 + h->big.bytes;
+    g->device_bytes += h->bytes;
+    g->hot = std::move(h);
+}
+
+void apply_tunables(bfs_graph* g, const bfs_tunables& r) {
+    const int32_t want_hot = hot_count(g, r);
+    const bool big_stale = r.wave_max_degree != g->big.threshold;
+    const bool hot_stale = want_hot != (g->hot ? g->hot->hot : 0) ||
+                           (g->hot && g->hot->big.threshold != r.wave_max_degree);
+    if (big_stale || hot_stale) {
+        // Tables are shared by every run on the graph: rebuild them only after
+        // in-flight work has drained. Workspaces hold lists sized for the old
+        // tables: drop them.
+        BFS_HIP(hipDeviceSynchronize());
+        std::lock_guard<std::mutex> lk(g->mu);
+        for (auto* w : g->ws_all) g->device_bytes -= w->bytes;
+        for (auto* w : g->ms_all) g->device_bytes -= w->bytes;
+        free_workspaces(g);
+        if (big_stale) {
+            g->device_bytes -= g->big.bytes;
+            build_big_table(g->big, g->d_off, g->off32, g->n, r.wave_max_degree, g->restore_grid, g->cu_count,
+                            &g->max_degree);
+            g->device_bytes += g->big.bytes;
+        }
+        if (want_hot != (g->hot ? g->hot->hot : 0)) {
+            build_hot_layout(g, want_hot, r.wave_max_degree);
+        } else if (g->hot && g->hot->big.threshold != r.wave_max_degree) {
+            HotLayout& h = *g->hot;
+            g->device_bytes -= h.big.bytes;
+            h.bytes -= h.big.bytes;
+            build_big_table(h.big, h.d_off, false, g->n, r.wave_max_degree, g->restore_grid, g->cu_count, nullptr);
+            g->device_bytes += h.big.bytes;
+            h.bytes += h.big.bytes;
+        }
+    }
+    g->tun = r;
 }
 
 bfs_tunables default_tunables(const bfs_graph* g) {
@@ -127,6 +273,14 @@ bfs_tunables default_tunables(const bfs_graph* g) {
     t.blocks_per_cu = 0;  // 0 = as many as fit (occupancy query at launch)
     t.batch_width = 64;
     t.update_mode = 1;
+    // From 2^22 vertices on, single-root runs use the degree-ordered copy with
+    // an LDS bitmap of the 2^19 highest-degree vertices (64 KiB), shared by the
+    // 16 wavefronts of a 1024-thread workgroup.
+    // Only skewed degree distributions concentrate probes on few vertices.
+    const bool large = g && g->n >= (int64_t)1 << 22 &&
+                       g->max_degree > 64 * std::max<int64_t>(1, g->nnz / std::max<int64_t>(1, g->n));
+    t.hot_vertices = large ? 1 << 19 : -1;
+    if (large) t.block_size = 1024;
     return t;
 }
 
@@ -138,10 +292,13 @@ bfs_tunables resolve_tunables(const bfs_graph* g, const bfs_tunables& in) {
     if (t.wave_max_degree <= 0) t.wave_max_degree = d.wave_max_degree;
     if (t.wave_max_degree < t.small_max_degree) t.wave_max_degree = t.small_max_degree;
     if (t.chunk_arcs < 0) t.chunk_arcs = 0;
-    if (t.block_size != 256 && t.block_size != 512) t.block_size = d.block_size;
+    if (t.block_size != 256 && t.block_size != 512 && t.block_size != 1024) t.block_size = d.block_size;
     if (t.blocks_per_cu < 0) t.blocks_per_cu = 0;
     if (t.batch_width <= 0 || t.batch_width > 64) t.batch_width = d.batch_width;
     if (t.update_mode != 1 && t.update_mode != 2) t.update_mode = d.update_mode;
+    if (t.hot_vertices == 0) t.hot_vertices = d.hot_vertices;
+    if (t.hot_vertices < 0) t.hot_vertices = -1;
+    if (t.hot_vertices > kMaxHotWords * 32) t.hot_vertices = kMaxHotWords * 32;
     return t;
 }
 
@@ -168,10 +325,13 @@ Workspace* acquire_ws(bfs_graph* g, hipStream_t s) {
         w->device = g->device;
         w->words = padded_words(g->n);
         w->nslots = (int64_t)g->cu_count * 64 + 64;  // >= any expansion or restore grid
-        w->big_capacity = std::max(g->num_big, 1);
+        w->big_capacity = std::max(g->big.num_big, 1);
         const size_t bmb = (size_t)w->words * 4;
         const size_t listb = (size_t)w->big_capacity * 8 + (size_t)(g->restore_grid + 1) * 8;
-        const size_t total = bmb * 3 + sizeof(Ctrl) + (size_t)w->nslots * 2 * 8 + listb;
+        w->hot_capacity = (int)std::min<int64_t>(w->words / 32, kMaxHotWords);
+        const size_t hotb = (size_t)w->hot_capacity * 4;
+        const size_t lvb = g->hot ? (size_t)g->n * 4 : 0;  // levels in the degree-ordered ids
+        const size_t total = bmb * 3 + sizeof(Ctrl) + (size_t)w->nslots * 2 * 8 + listb + hotb + lvb;
         char* base = nullptr;
         BFS_HIP(hipMalloc(&base, total));
         w->vis = reinterpret_cast<uint32_t*>(base);
@@ -184,6 +344,8 @@ Workspace* acquire_ws(bfs_graph* g, hipStream_t s) {
         w->bl_pre = reinterpret_cast<uint32_t*>(lp + (size_t)w->big_capacity * 4);
         w->seg_cnt = reinterpret_cast<uint32_t*>(lp + (size_t)w->big_capacity * 8);
         w->seg_arcs = w->seg_cnt + (g->restore_grid + 1);
+        w->hot_vis = reinterpret_cast<uint32_t*>(lp + listb);
+        w->lv_new = lvb ? reinterpret_cast<int32_t*>(lp + listb + hotb) : nullptr;
         BFS_HIP(hipMemset(w->ctrl, 0, sizeof(Ctrl)));
         BFS_HIP(hipHostMalloc(&w->host_ctrl, sizeof(Ctrl), hipHostMallocDefault));
         BFS_HIP(hipEventCreate(&w->ev_start));
@@ -291,6 +453,7 @@ void free_workspaces(bfs_graph* g) {
 bfs_graph* load_csr(int64_t n, int64_t nnz, const void* offsets, const int32_t* cols, uint32_t flags) {
     if (n < 1 || n > 2147483647LL) fail(BFS_E_INVALID_GRAPH, "n out of range");
     if (nnz < 0) fail(BFS_E_INVALID_GRAPH, "nnz < 0");
+    if (nnz > 4294967295LL) fail(BFS_E_INVALID_GRAPH, "nnz above 2^32 - 1 (arc offsets of the big-row lists are 32-bit)");
     if (!offsets || (!cols && nnz > 0)) fail(BFS_E_INVALID_ARG, "NULL CSR array");
     if (flags & ~(BFS_LOAD_DEVICE_PTRS | BFS_LOAD_SKIP_VALIDATE | BFS_LOAD_OFFSETS_I32))
         fail(BFS_E_INVALID_ARG, "unknown load flag");
@@ -324,19 +487,20 @@ bfs_graph* load_csr(int64_t n, int64_t nnz, const void* offsets, const int32_t* 
             if (nnz) BFS_HIP(hipMemcpy(g->d_col, cols, (size_t)nnz * 4, hipMemcpyHostToDevice));
             g->device_bytes += (int64_t)ob + nnz * 4;
         }
-        g->tun = default_tunables(g);
-        rebuild_big(g, g->tun.wave_max_degree);
-        g->device_bytes += (int64_t)std::max(g->num_big, 1) * 4 + (int64_t)(g->num_big + 1) * 8 +
-                           padded_words(n) * 4;
+        g->restore_grid = restore_grid_for(padded_words(n), g->cu_count);
+        build_big_table(g->big, g->d_off, g->off32, n, default_tunables(nullptr).wave_max_degree, g->restore_grid,
+                        g->cu_count, &g->max_degree);
+        g->device_bytes += g->big.bytes;
+        const bfs_tunables t = default_tunables(g);  // depends on the degrees just read
+        build_hot_layout(g, hot_count(g, t), t.wave_max_degree);
+        g->tun = t;
     } catch (...) {
         if (g->owns) {
             if (g->d_off) (void)hipFree(g->d_off);
             if (g->d_col) (void)hipFree(g->d_col);
         }
-        if (g->d_big) (void)hipFree(g->d_big);
-        if (g->d_big_prefix) (void)hipFree(g->d_big_prefix);
-        if (g->d_bigmap) (void)hipFree(g->d_bigmap);
-        if (g->d_seg_start) (void)hipFree(g->d_seg_start);
+        free_big_table(g->big);
+        free_hot_layout(g);
         delete g;
         throw;
     }
@@ -351,10 +515,8 @@ void free_graph(bfs_graph* g) {
         (void)hipFree(g->d_off);
         (void)hipFree(g->d_col);
     }
-    if (g->d_big) (void)hipFree(g->d_big);
-    if (g->d_big_prefix) (void)hipFree(g->d_big_prefix);
-    if (g->d_bigmap) (void)hipFree(g->d_bigmap);
-    if (g->d_seg_start) (void)hipFree(g->d_seg_start);
+    free_big_table(g->big);
+    free_hot_layout(g);
     delete g;
 }
 

@@ -565,11 +565,11 @@ MsParams make_params(bfs_graph* g, const bfs_tunables& t, MsWorkspace* w, int lv
     p.fr = w->fr[lvl & 1];
     p.nfr = w->fr[(lvl + 1) & 1];
     p.ctrl = w->ctrl;
-    p.big = g->d_big;
-    p.big_prefix = g->d_big_prefix;
-    p.bigmap = g->d_bigmap;
-    p.num_big = g->num_big;
-    p.big_arcs = g->big_arcs;
+    p.big = g->big.d_big;
+    p.big_prefix = g->big.d_big_prefix;
+    p.bigmap = g->big.d_bigmap;
+    p.num_big = g->big.num_big;
+    p.big_arcs = g->big.big_arcs;
     p.t1 = t.small_max_degree;
     return p;
 }
@@ -580,7 +580,7 @@ int dense_grid(bfs_graph* g, int64_t n) {
 
 template <typename OffT>
 void enqueue_level(bfs_graph* g, const bfs_tunables& t, MsWorkspace* w, int lvl, bool per_slot, hipStream_t s) {
-    if (g->big_threshold != t.wave_max_degree) fail(BFS_E_INTERNAL, "big-row table out of date");
+    if (g->big.threshold != t.wave_max_degree) fail(BFS_E_INTERNAL, "big-row table out of date");
     MsParams p = make_params(g, t, w, lvl);
     static const int occ = occupancy_of(k_ms_push<OffT, 256>, 256);
     const int bpc = t.blocks_per_cu > 0 && (occ < 1 || t.blocks_per_cu < occ) ? t.blocks_per_cu : (occ > 0 ? occ : 1);

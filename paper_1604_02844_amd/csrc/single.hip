@@ -53,7 +53,9 @@ namespace bfs {
 
 namespace {
 
-constexpr int kUnroll = 2;  // arcs per lane in flight per expansion step
+constexpr int kUnroll = 2;     // arcs per lane in flight: one wavefront per row (T1 < d <= T2)
+constexpr int kLbsUnroll = 4;  // arcs per lane in flight: packed rows (d <= T1)
+constexpr int kBigUnroll = 4;  // arcs per lane in flight: rows above T2
 
 struct SingleParams {
     const void* off;
@@ -61,8 +63,11 @@ struct SingleParams {
     int32_t n;
     int32_t root;
     int64_t words;  // padded 32-bit words per bitmap (multiple of 64)
-    int32_t* levels;
-    int32_t* parents;
+    int32_t* lv;               // levels by the run's vertex ids (read by restore and claims)
+    int32_t* out_lv;           // the caller's levels and parents, by caller ids
+    int32_t* out_pa;
+    const int32_t* new2old;    // run id -> caller id on the degree-ordered copy, else nullptr
+    int32_t root_out;          // the root as a caller id
     uint32_t* vis;
     uint32_t* vis_prev;
     uint32_t* fr;
@@ -77,9 +82,15 @@ struct SingleParams {
     const int32_t* seg_start; // first list slot of each segment
     int32_t restore_grid;
     int32_t t1;
+    int32_t min_share;         // fewest big-row arcs handed to one workgroup
+    // Hot vertices sit at ids 32r (r < 32 * hot_words): bit 0 of visited word r.
+    // hot_vis is their compact visited bitmap (bit r), which the restore pass
+    // keeps exact and expansion workgroups copy into LDS.
+    uint32_t* hot_vis;
+    int32_t hot_words;         // words of hot_vis (0 = off)
+    int64_t hot_min_frontier;  // use the LDS copy only for frontiers of at least this many vertices
 };
 
-constexpr int kMinBigShare = 1024;  // fewest big-row arcs handed to one workgroup
 
 // Cross-kernel shared state (bitmaps, level array, lists, counters) is read and
 // written with device-scope accesses: each XCD has its own L2, and a plain load
@@ -152,15 +163,35 @@ __device__ __forceinline__ unsigned long long* stripe(Ctrl* c, int parity, int s
 
 // Visit up to U arcs per lane: gather neighbour ids, filter on the visited
 // word, then mark (plain read-modify-write or atomicOr) and write level/parent.
+// Caller id of run id u.
+__device__ __forceinline__ int32_t out_id(const SingleParams& p, int32_t u) { return p.new2old ? p.new2old[u] : u; }
+
+// Discovery of run id v at level lvl from the caller-id parent par.
+__device__ __forceinline__ void record(const SingleParams& p, int32_t v, int lvl, int32_t par) {
+    p.lv[v] = lvl;
+    const int32_t o = out_id(p, v);
+    if (p.new2old) p.out_lv[o] = lvl;
+    p.out_pa[o] = par;
+}
+
+// Hot ids (32r with r < hot_limit) are first looked up in the workgroup's LDS
+// copy of the compact hot bitmap (taken at the start of the level, so a set bit
+// is final); only the rest, and hot ids not yet visited, probe the global bitmap.
 template <bool kAtomic, int U>
 __device__ __forceinline__ void visit_arcs(const SingleParams& p, const int64_t (&pos)[U], const bool (&ok)[U],
-                                           const int32_t (&par)[U], int lvl) {
+                                           const int32_t (&par)[U], int lvl, uint32_t* hot, uint32_t hot_limit) {
     int32_t v[U];
 #pragma unroll
     for (int i = 0; i < U; ++i) v[i] = ok[i] ? __builtin_nontemporal_load(p.col + pos[i]) : 0;
     uint32_t w[U];
+    bool in_hot[U];
 #pragma unroll
-    for (int i = 0; i < U; ++i) w[i] = ok[i] ? p.vis[v[i] >> 5] : ~0u;
+    for (int i = 0; i < U; ++i) {
+        const uint32_t r = (uint32_t)v[i] >> 5;
+        in_hot[i] = ok[i] && (v[i] & 31) == 0 && r < hot_limit;
+        const bool known = in_hot[i] && ((hot[r >> 5] >> (r & 31)) & 1u);
+        w[i] = (ok[i] && !known) ? p.vis[r] : ~0u;
+    }
     if (kAtomic) {
         uint32_t old[U];
         bool need[U];
@@ -174,10 +205,8 @@ __device__ __forceinline__ void visit_arcs(const SingleParams& p, const int64_t 
 #pragma unroll
         for (int i = 0; i < U; ++i) {
             const uint32_t b = 1u << (v[i] & 31);
-            if (need[i] && !(old[i] & b)) {
-                p.levels[v[i]] = lvl;
-                p.parents[v[i]] = par[i];
-            }
+            if (need[i] && !(old[i] & b)) record(p, v[i], lvl, par[i]);
+            if (need[i] && in_hot[i]) atomicOr(hot + (v[i] >> 10), 1u << ((v[i] >> 5) & 31));
         }
     } else {
         // The plain load above is only a filter: its line may be stale in this
@@ -186,22 +215,22 @@ __device__ __forceinline__ void visit_arcs(const SingleParams& p, const int64_t 
         // reached in any earlier level.
         int lv_now[U];
 #pragma unroll
-        for (int i = 0; i < U; ++i) lv_now[i] = (!(w[i] & (1u << (v[i] & 31)))) ? ld(p.levels + v[i]) : 0;
+        for (int i = 0; i < U; ++i) lv_now[i] = (!(w[i] & (1u << (v[i] & 31)))) ? ld(p.lv + v[i]) : 0;
 #pragma unroll
         for (int i = 0; i < U; ++i) {
             const uint32_t b = 1u << (v[i] & 31);
             if (!(w[i] & b) && lv_now[i] == -1) {
                 p.vis[v[i] >> 5] = w[i] | b;  // may lose a concurrent update: restored later
-                p.levels[v[i]] = lvl;
-                p.parents[v[i]] = par[i];
+                record(p, v[i], lvl, par[i]);
             }
+            if (!(w[i] & b) && in_hot[i]) atomicOr(hot + (v[i] >> 10), 1u << ((v[i] >> 5) & 31));  // this workgroup's later probes
         }
     }
 }
 
 template <bool kAtomic, int U>
 __device__ __forceinline__ void expand_row(const SingleParams& p, int64_t beg, int64_t d, int32_t u, int t,
-                                           int nthreads, int lvl) {
+                                           int nthreads, int lvl, uint32_t* hot, uint32_t hot_limit) {
     for (int64_t j0 = 0; j0 < d; j0 += (int64_t)nthreads * U) {
         int64_t pos[U];
         bool ok[U];
@@ -213,7 +242,7 @@ __device__ __forceinline__ void expand_row(const SingleParams& p, int64_t beg, i
             pos[i] = beg + j;
             par[i] = u;
         }
-        visit_arcs<kAtomic, U>(p, pos, ok, par, lvl);
+        visit_arcs<kAtomic, U>(p, pos, ok, par, lvl, hot, hot_limit);
     }
 }
 
@@ -222,11 +251,13 @@ __device__ __forceinline__ void expand_row(const SingleParams& p, int64_t beg, i
 // with excl[e] <= a < incl[e]. Larger rows get the whole wavefront each.
 template <typename OffT, bool kAtomic>
 __device__ __forceinline__ void process_batch(const SingleParams& p, int32_t u, bool valid, int lane, int lvl,
-                                              unsigned long long& arcs) {
+                                              unsigned long long& arcs, uint32_t* hot, uint32_t hot_limit) {
     int64_t beg = 0, d = 0;
+    int32_t uo = 0;  // the row as a caller id: the parent of its discoveries
     if (valid) {
         beg = load_off<OffT>(p.off, u);
         d = load_off<OffT>(p.off, (int64_t)u + 1) - beg;
+        uo = out_id(p, u);
     }
     arcs += (unsigned long long)d;
     const bool small = valid && d <= p.t1;
@@ -234,12 +265,12 @@ __device__ __forceinline__ void process_batch(const SingleParams& p, int32_t u, 
     const int incl = wave_incl_scan(ds, lane);
     const int excl = incl - ds;
     const int total = __shfl(incl, 63, 64);
-    for (int base = 0; base < total; base += 64 * kUnroll) {
-        int64_t pos[kUnroll];
-        bool ok[kUnroll];
-        int32_t par[kUnroll];
+    for (int base = 0; base < total; base += 64 * kLbsUnroll) {
+        int64_t pos[kLbsUnroll];
+        bool ok[kLbsUnroll];
+        int32_t par[kLbsUnroll];
 #pragma unroll
-        for (int i = 0; i < kUnroll; ++i) {
+        for (int i = 0; i < kLbsUnroll; ++i) {
             const int a = base + i * 64 + lane;
             ok[i] = a < total;
             const int ac = ok[i] ? a : total - 1;
@@ -254,34 +285,158 @@ __device__ __forceinline__ void process_batch(const SingleParams& p, int32_t u, 
             }
             const int ex = __shfl(excl, lo, 64);
             const int64_t b = shfl64(beg, lo);
-            par[i] = __shfl(u, lo, 64);
+            par[i] = __shfl(uo, lo, 64);
             pos[i] = b + (ac - ex);
         }
-        visit_arcs<kAtomic, kUnroll>(p, pos, ok, par, lvl);
+        visit_arcs<kAtomic, kLbsUnroll>(p, pos, ok, par, lvl, hot, hot_limit);
     }
     uint64_t mm = __ballot(valid && !small && d > 0);
     while (mm) {
         const int e = __builtin_ctzll(mm);
         mm &= mm - 1;
-        expand_row<kAtomic, kUnroll>(p, shfl64(beg, e), shfl64(d, e), __shfl(u, e, 64), lane, 64, lvl);
+        expand_row<kAtomic, kUnroll>(p, shfl64(beg, e), shfl64(d, e), __shfl(uo, e, 64), lane, 64, lvl, hot,
+                                     hot_limit);
     }
 }
-
-constexpr int kMaxRestoreGrid = 2048;
 
 template <int BLOCK>
 struct ExpandShared {
     static constexpr int NW = BLOCK / 64;
-    uint32_t ring[NW][128];
-    uint32_t segpre[kMaxRestoreGrid + 1];  // exclusive prefix of segment arcs
+    union {
+        uint32_t ring[NW][128];  // staged frontier vertices, one ring per wavefront
+        struct {
+            uint32_t segpre[kMaxRestoreGrid + 1];  // exclusive prefix of segment arcs
+            uint32_t cntpre[kMaxRestoreGrid + 1];  // exclusive prefix of segment rows
+            int64_t start[BLOCK];  // first arc (level-wide numbering, clipped to the share) of a staged row
+            int64_t base[BLOCK];   // column index minus arc number for that row
+            int32_t u[BLOCK];      // the row's vertex as a caller id
+        } big;
+    } x;
     uint32_t tmp[BLOCK / 64];
     unsigned long long red[NW];
     unsigned long long found;
     unsigned long long big_total;
-    int64_t row_beg;   // broadcast of the big row being expanded
-    int64_t row_len;
-    int32_t row_u;
+    int64_t staged_end;  // last arc (exclusive) of the staged big rows
+    uint32_t row0;
 };
+
+// Rows above T2: this workgroup's share [a0, a1) of the level's concatenated
+// big-row arcs. Row metadata is staged BLOCK rows at a time (every thread loads
+// one row), then every thread takes kBigUnroll arcs per step and finds its row
+// by binary search over the staged starts: all lanes stay busy whatever the
+// row lengths, and no thread walks rows serially.
+template <typename OffT, bool kAtomic, int BLOCK>
+__device__ __forceinline__ void expand_big(const SingleParams& p, ExpandShared<BLOCK>& sh, int64_t a0, int64_t a1,
+                                           int lvl, unsigned long long& arcs, uint32_t* hot, uint32_t hot_limit) {
+    const int tid = threadIdx.x;
+    const int R = p.restore_grid;
+    constexpr int PER_T = (kMaxRestoreGrid + BLOCK) / BLOCK;  // covers entries 0..R inclusive
+    // Prefix sums over the segments (one per restore block): arcs and rows.
+    uint32_t va[PER_T], vc[PER_T];
+    uint32_t ma = 0, mc = 0;
+#pragma unroll
+    for (int k = 0; k < PER_T; ++k) {
+        const int i = tid * PER_T + k;
+        va[k] = i < R ? ld(p.seg_arcs + i) : 0u;
+        vc[k] = i < R ? ld(p.seg_cnt + i) : 0u;
+        ma += va[k];
+        mc += vc[k];
+    }
+    uint32_t ea, ec;
+    block_excl_scan<BLOCK>(ma, ea, sh.tmp);
+    block_excl_scan<BLOCK>(mc, ec, sh.tmp);
+#pragma unroll
+    for (int k = 0; k < PER_T; ++k) {
+        const int i = tid * PER_T + k;
+        if (i <= R) {
+            sh.x.big.segpre[i] = ea;
+            sh.x.big.cntpre[i] = ec;
+        }
+        ea += va[k];
+        ec += vc[k];
+    }
+    __syncthreads();
+    const uint32_t total_rows = sh.x.big.cntpre[R];
+    // The row holding arc a0: its segment by the arc prefix, then its index
+    // inside the segment by the stored arc offsets.
+    if (tid == 0) {
+        // Last segment starting at or before a0; as a0 < total, the next
+        // segment starts after a0, so this one holds arcs.
+        int lo = 0, hi = R - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if ((int64_t)sh.x.big.segpre[mid] <= a0)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const int64_t local = a0 - (int64_t)sh.x.big.segpre[lo];
+        const int first = p.seg_start[lo];
+        int l2 = 0, h2 = (int)(sh.x.big.cntpre[lo + 1] - sh.x.big.cntpre[lo]) - 1;
+        while (l2 < h2) {
+            const int mid = (l2 + h2 + 1) >> 1;
+            if ((int64_t)ld(p.bl_pre + first + mid) <= local)
+                l2 = mid;
+            else
+                h2 = mid - 1;
+        }
+        sh.row0 = sh.x.big.cntpre[lo] + (uint32_t)l2;
+    }
+    __syncthreads();
+    uint32_t d0 = sh.row0;
+    int64_t from = a0;
+    while (from < a1 && d0 < total_rows) {
+        // Stage rows d0 .. d0+BLOCK-1 (dense numbering across segments).
+        const uint32_t d = d0 + (uint32_t)tid;
+        const int nt = (int)min((uint32_t)BLOCK, total_rows - d0);
+        int64_t end = a1;
+        if (tid < nt) {
+            int lo = 0, hi = R - 1;  // last segment whose first row is <= d (non-empty by construction)
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (sh.x.big.cntpre[mid] <= d)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            const int slot = p.seg_start[lo] + (int)(d - sh.x.big.cntpre[lo]);
+            const int32_t u = ld(p.bl_u + slot);
+            const int64_t start = (int64_t)sh.x.big.segpre[lo] + ld(p.bl_pre + slot);
+            const int64_t beg = load_off<OffT>(p.off, u);
+            const int64_t deg = load_off<OffT>(p.off, (int64_t)u + 1) - beg;
+            sh.x.big.start[tid] = start > from ? start : from;
+            sh.x.big.base[tid] = beg - start;
+            sh.x.big.u[tid] = out_id(p, u);
+            end = start + deg < a1 ? start + deg : a1;
+        }
+        if (tid == nt - 1) sh.staged_end = end;
+        __syncthreads();
+        const int64_t hi_arc = sh.staged_end;
+        for (int64_t b = from; b < hi_arc; b += (int64_t)BLOCK * kBigUnroll) {
+            int64_t pos[kBigUnroll];
+            bool ok[kBigUnroll];
+            int32_t par[kBigUnroll];
+#pragma unroll
+            for (int i = 0; i < kBigUnroll; ++i) {
+                const int64_t a = b + (int64_t)i * BLOCK + tid;
+                ok[i] = a < hi_arc;
+                int lo = 0, hi = nt - 1;  // last staged row starting at or before a
+#pragma unroll
+                for (int st_ = 0; st_ < 31 - __builtin_clz(BLOCK); ++st_) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (sh.x.big.start[mid] <= a) lo = mid; else hi = mid - 1;
+                }
+                pos[i] = sh.x.big.base[lo] + a;
+                par[i] = sh.x.big.u[lo];
+            }
+            visit_arcs<kAtomic, kBigUnroll>(p, pos, ok, par, lvl, hot, hot_limit);
+        }
+        if (tid == 0) arcs += (unsigned long long)(hi_arc - from);
+        from = hi_arc;
+        d0 += (uint32_t)nt;
+        __syncthreads();
+    }
+}
 
 // a0: levels/parents = -1, bitmaps cleared, root seeded, counters reset.
 template <typename OffT, int BLOCK>
@@ -289,26 +444,40 @@ __global__ __launch_bounds__(BLOCK) void k_init(SingleParams p, int nslots) {
     const int64_t gtid = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     const int64_t gsize = (int64_t)gridDim.x * BLOCK;
     const int64_t n4 = p.n / 4;
-    const bool aligned = ((reinterpret_cast<uintptr_t>(p.levels) | reinterpret_cast<uintptr_t>(p.parents)) & 15) == 0;
+    // Caller outputs (caller ids), and on the degree-ordered copy also the
+    // run's own level array.
+    const int ro = p.root_out;
+    const bool aligned = ((reinterpret_cast<uintptr_t>(p.out_lv) | reinterpret_cast<uintptr_t>(p.out_pa) |
+                           reinterpret_cast<uintptr_t>(p.lv)) & 15) == 0;
     if (aligned) {
-        int4* lv4 = reinterpret_cast<int4*>(p.levels);
-        int4* pa4 = reinterpret_cast<int4*>(p.parents);
+        int4* lv4 = reinterpret_cast<int4*>(p.out_lv);
+        int4* pa4 = reinterpret_cast<int4*>(p.out_pa);
+        int4* in4 = reinterpret_cast<int4*>(p.lv);
         for (int64_t i = gtid; i < n4; i += gsize) {
-            int4 a = make_int4(-1, -1, -1, -1), b = make_int4(-1, -1, -1, -1);
+            int4 a = make_int4(-1, -1, -1, -1), b = make_int4(-1, -1, -1, -1), c = make_int4(-1, -1, -1, -1);
+            if ((ro >> 2) == i) {
+                const int k = ro & 3;
+                if (k == 0) { a.x = 0; b.x = ro; }
+                if (k == 1) { a.y = 0; b.y = ro; }
+                if (k == 2) { a.z = 0; b.z = ro; }
+                if (k == 3) { a.w = 0; b.w = ro; }
+            }
             if ((p.root >> 2) == i) {
                 const int k = p.root & 3;
-                if (k == 0) { a.x = 0; b.x = p.root; }
-                if (k == 1) { a.y = 0; b.y = p.root; }
-                if (k == 2) { a.z = 0; b.z = p.root; }
-                if (k == 3) { a.w = 0; b.w = p.root; }
+                if (k == 0) c.x = 0;
+                if (k == 1) c.y = 0;
+                if (k == 2) c.z = 0;
+                if (k == 3) c.w = 0;
             }
             lv4[i] = a;
             pa4[i] = b;
+            if (p.new2old) in4[i] = c;
         }
     }
     for (int64_t i = (aligned ? n4 * 4 : 0) + gtid; i < p.n; i += gsize) {
-        p.levels[i] = (i == p.root) ? 0 : -1;
-        p.parents[i] = (i == p.root) ? p.root : -1;
+        p.out_lv[i] = (i == ro) ? 0 : -1;
+        p.out_pa[i] = (i == ro) ? ro : -1;
+        if (p.new2old) p.lv[i] = (i == p.root) ? 0 : -1;
     }
     const int64_t rw = p.root >> 5;
     const uint32_t rb = 1u << (p.root & 31);
@@ -322,6 +491,9 @@ __global__ __launch_bounds__(BLOCK) void k_init(SingleParams p, int nslots) {
         p.arcs_slot[i] = 0;
         p.reached_slot[i] = 0;
     }
+    const bool root_hot = (p.root & 31) == 0 && rw < (int64_t)p.hot_words * 32;
+    for (int64_t i = gtid; i < p.hot_words; i += gsize)
+        p.hot_vis[i] = (root_hot && i == (rw >> 5)) ? 1u << (rw & 31) : 0u;
     // The root is the whole first frontier; when its row is big it is the only
     // entry of the big-row list (in the segment of its restore block).
     const bool root_big = (p.bigmap[rw] >> (p.root & 31)) & 1u;
@@ -374,6 +546,17 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl) {
     }
     unsigned long long arcs = 0;
 
+    // ---- LDS copy of the compact hot bitmap (exact at level start)
+    extern __shared__ uint32_t hot_lds[];
+    uint32_t hot_limit = 0;
+    if (p.hot_words > 0 && (int64_t)sh.found >= p.hot_min_frontier) {
+        const unsigned long long* src = reinterpret_cast<const unsigned long long*>(p.hot_vis);
+        unsigned long long* dst = reinterpret_cast<unsigned long long*>(hot_lds);
+        for (int i = tid; i < p.hot_words / 2; i += BLOCK) dst[i] = ld(src + i);
+        hot_limit = (uint32_t)p.hot_words * 32u;
+        __syncthreads();
+    }
+
     // ---- rows of degree > T2: the level's big-row arcs, split evenly
     if (tid < 64) {
         unsigned long long c = ld(&p.ctrl->bigarcs[lvl & 1][tid * kStripeStride]);
@@ -385,86 +568,10 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl) {
     const int64_t ta = (int64_t)sh.big_total;
     if (ta > 0) {
         int64_t per = (ta + G - 1) / G;
-        if (per < kMinBigShare) per = kMinBigShare;
+        if (per < p.min_share) per = p.min_share;
         const int64_t a0 = bid * per;
         const int64_t a1 = a0 + per < ta ? a0 + per : ta;
-        if (a0 < a1) {
-            // Exclusive prefix of the segment totals (one segment per restore block).
-            const int R = p.restore_grid;
-            constexpr int PER_T = (kMaxRestoreGrid + BLOCK - 1) / BLOCK;
-            uint32_t vals[PER_T];
-            uint32_t mine = 0;
-#pragma unroll
-            for (int k = 0; k < PER_T; ++k) {
-                const int i = tid * PER_T + k;
-                vals[k] = i < R ? ld(p.seg_arcs + i) : 0u;
-                mine += vals[k];
-            }
-            uint32_t excl;
-            block_excl_scan<BLOCK>(mine, excl, sh.tmp);
-#pragma unroll
-            for (int k = 0; k < PER_T; ++k) {
-                const int i = tid * PER_T + k;
-                if (i <= R) sh.segpre[i] = excl;
-                excl += vals[k];
-            }
-            __syncthreads();
-            // Walk the rows covering [a0, a1): thread 0 locates each piece, the
-            // whole workgroup expands it.
-            int seg = 0, idx = 0;
-            if (tid == 0) {
-                int lo = 0, hi = R - 1;  // last segment with segpre <= a0
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if ((int64_t)sh.segpre[mid] <= a0)
-                        lo = mid;
-                    else
-                        hi = mid - 1;
-                }
-                while (lo < R - 1 && (int64_t)sh.segpre[lo + 1] <= a0) ++lo;
-                seg = lo;
-                const int64_t local = a0 - (int64_t)sh.segpre[seg];
-                const int first = p.seg_start[seg];
-                int l2 = 0, h2 = (int)ld(p.seg_cnt + seg) - 1;  // last row with offset <= local
-                while (l2 < h2) {
-                    const int mid = (l2 + h2 + 1) >> 1;
-                    if ((int64_t)ld(p.bl_pre + first + mid) <= local)
-                        l2 = mid;
-                    else
-                        h2 = mid - 1;
-                }
-                idx = l2;
-            }
-            int64_t pos = a0;
-            while (pos < a1) {
-                if (tid == 0) {
-                    while (seg < R && idx >= (int)ld(p.seg_cnt + seg)) {  // next non-empty segment
-                        ++seg;
-                        idx = 0;
-                    }
-                }
-                if (tid == 0 && seg >= R) sh.row_len = 0;  // list exhausted (cannot happen: a1 <= total)
-                if (tid == 0 && seg < R) {
-                    const int slot = p.seg_start[seg] + idx;
-                    const int32_t u = ld(p.bl_u + slot);
-                    const int64_t row_start = (int64_t)sh.segpre[seg] + ld(p.bl_pre + slot);
-                    const int64_t beg = load_off<OffT>(p.off, u);
-                    const int64_t deg = load_off<OffT>(p.off, (int64_t)u + 1) - beg;
-                    const int64_t end = row_start + deg < a1 ? row_start + deg : a1;
-                    sh.row_u = u;
-                    sh.row_beg = beg + (pos - row_start);
-                    sh.row_len = end - pos;
-                    ++idx;
-                }
-                __syncthreads();
-                const int64_t len = sh.row_len;
-                if (len <= 0) break;
-                expand_row<kAtomic, kUnroll>(p, sh.row_beg, len, sh.row_u, tid, BLOCK, lvl + 1);
-                if (tid == 0) arcs += (unsigned long long)len;
-                pos += len;
-                __syncthreads();
-            }
-        }
+        if (a0 < a1) expand_big<OffT, kAtomic, BLOCK>(p, sh, a0, a1, lvl + 1, arcs, hot_lds, hot_limit);
     }
 
     // ---- every other frontier vertex: a contiguous run of words per wavefront
@@ -484,21 +591,21 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl) {
             if (has) {
                 const int bit = __builtin_ctz(word);
                 word &= word - 1;
-                sh.ring[wid][(tail + rank_in(m)) & 127] = (uint32_t)(wi * 32 + bit);
+                sh.x.ring[wid][(tail + rank_in(m)) & 127] = (uint32_t)(wi * 32 + bit);
             }
             tail += __popcll(m);
             if (tail - head >= 64) {
-                const int32_t u = (int32_t)sh.ring[wid][(head + lane) & 127];
+                const int32_t u = (int32_t)sh.x.ring[wid][(head + lane) & 127];
                 head += 64;
-                process_batch<OffT, kAtomic>(p, u, true, lane, lvl + 1, arcs);
+                process_batch<OffT, kAtomic>(p, u, true, lane, lvl + 1, arcs, hot_lds, hot_limit);
             }
         }
     }
     if (tail != head) {
         const int cnt = (int)(tail - head);
         const bool valid = lane < cnt;
-        const int32_t u = valid ? (int32_t)sh.ring[wid][(head + lane) & 127] : 0;
-        process_batch<OffT, kAtomic>(p, u, valid, lane, lvl + 1, arcs);
+        const int32_t u = valid ? (int32_t)sh.x.ring[wid][(head + lane) & 127] : 0;
+        process_batch<OffT, kAtomic>(p, u, valid, lane, lvl + 1, arcs, hot_lds, hot_limit);
     }
 
     // ---- block total of scanned arcs (plain update of this block's own slot)
@@ -558,7 +665,7 @@ __global__ __launch_bounds__(kRestoreBlock) void k_restore(SingleParams p, int l
                 const int src = lane < 32 ? wa : wb;
                 const int64_t v = (wave_w0 + src) * 32 + (lane & 31);
                 const bool okl = src >= 0 && v < p.n;
-                const int lvv = okl ? ld(p.levels + v) : -1;
+                const int lvv = okl ? ld(p.lv + v) : -1;
                 const uint64_t m = __ballot(lvv == next);
                 if (lane == wa) exact = (uint32_t)m;
                 if (lane == wb) exact = (uint32_t)(m >> 32);
@@ -568,6 +675,17 @@ __global__ __launch_bounds__(kRestoreBlock) void k_restore(SingleParams p, int l
             const uint32_t nv = prev | exact;
             if (cur != nv) st(p.vis + w, nv);
             st(p.vis_prev + w, nv);
+        }
+        // Hot vertex of word w (id 32w) found this level: one compact word per
+        // half-wavefront, written by its first lane only.
+        if (p.hot_words > 0 && c * BLOCK < (int64_t)p.hot_words * 32) {
+            const uint64_t hm = __ballot(w < (int64_t)p.hot_words * 32 && (exact & 1u));
+            const int half = lane >> 5;
+            const uint32_t bits = (uint32_t)(hm >> (32 * half));
+            if ((lane & 31) == 0 && bits) {
+                uint32_t* hw = p.hot_vis + (w >> 5);
+                st(hw, ld(hw) | bits);
+            }
         }
         if (w < p.words) {
             st(p.fr + w, exact);
@@ -637,6 +755,21 @@ __global__ void k_stats(Ctrl* c, const unsigned long long* arcs_slot, const unsi
     }
 }
 
+// Columns of the degree-ordered copy: new row x is caller row new2old[x] with
+// every neighbour renamed; one wavefront per row, arcs in their original order.
+template <typename OffT>
+__global__ void k_relabel_cols(const OffT* off, const int32_t* col, const int64_t* noff, const int32_t* new2old,
+                               const int32_t* old2new, int32_t* ncol, int64_t n) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t x = wave; x < n; x += waves) {
+        const int64_t u = new2old[x];
+        const int64_t b = (int64_t)off[u], d = (int64_t)off[u + 1] - b, nb = noff[x];
+        for (int64_t j = lane; j < d; j += 64) ncol[nb + j] = old2new[col[b + j]];
+    }
+}
+
 template <typename OffT>
 __global__ void k_validate_csr(const OffT* off, const int32_t* col, int64_t n, int64_t nnz, int* err) {
     const int64_t gsize = (int64_t)gridDim.x * blockDim.x;
@@ -657,9 +790,9 @@ __global__ void k_fill_i32(int32_t* p, int64_t count, int32_t value) {
 }
 
 template <typename K>
-int occupancy_of(K kernel, int block) {
+int occupancy_of(K kernel, int block, size_t dyn_lds = 0) {
     int occ = 0;
-    hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, block, 0), "occupancy query");
+    hip_check(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, block, dyn_lds), "occupancy query");
     return occ;
 }
 
@@ -668,9 +801,15 @@ struct Grids {
     int restore;
 };
 
+
 template <typename OffT, int BLOCK, bool kAtomic>
-Grids grids_for(bfs_graph* g, const bfs_tunables& t, int64_t nslots) {
-    static const int occ = occupancy_of(k_expand<OffT, BLOCK, kAtomic>, BLOCK);
+Grids grids_for(bfs_graph* g, const bfs_tunables& t, int64_t nslots, int hot_words) {
+    // Dynamic LDS (the hot snapshot) beyond the default limit must be allowed once.
+    static const bool lds_ok = hipFuncSetAttribute(reinterpret_cast<const void*>(k_expand<OffT, BLOCK, kAtomic>),
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                   kMaxHotWords * 4) == hipSuccess;
+    if (!lds_ok) fail(BFS_E_DEVICE, "cannot enable dynamic LDS for the expansion kernel");
+    const int occ = occupancy_of(k_expand<OffT, BLOCK, kAtomic>, BLOCK, (size_t)hot_words * 4);
     const int bpc = t.blocks_per_cu > 0 && (occ < 1 || t.blocks_per_cu < occ) ? t.blocks_per_cu : (occ > 0 ? occ : 1);
     int64_t ge = (int64_t)bpc * g->cu_count;
     ge = std::max<int64_t>(1, std::min(ge, nslots));
@@ -681,7 +820,7 @@ Grids grids_for(bfs_graph* g, const bfs_tunables& t, int64_t nslots) {
 
 template <typename OffT, int BLOCK, bool kAtomic>
 void launch_typed(bfs_graph* g, const bfs_tunables& t, Workspace* w, SingleParams& p, hipStream_t s) {
-    const Grids gr = grids_for<OffT, BLOCK, kAtomic>(g, t, w->nslots);
+    const Grids gr = grids_for<OffT, BLOCK, kAtomic>(g, t, w->nslots, p.hot_words);
     const int init_grid = (int)std::min<int64_t>(std::max<int64_t>(p.n / 4, p.words) / BLOCK + 1, 4096);
     k_init<OffT, BLOCK><<<init_grid, BLOCK, 0, s>>>(p, (int)w->nslots);
     BFS_HIP(hipGetLastError());
@@ -690,7 +829,7 @@ void launch_typed(bfs_graph* g, const bfs_tunables& t, Workspace* w, SingleParam
     int chunk = 8;
     while (true) {
         for (int i = 0; i < chunk; ++i) {
-            k_expand<OffT, BLOCK, kAtomic><<<gr.expand, BLOCK, 0, s>>>(p, lvl + i);
+            k_expand<OffT, BLOCK, kAtomic><<<gr.expand, BLOCK, (size_t)p.hot_words * 4, s>>>(p, lvl + i);
             k_restore<OffT, kAtomic><<<gr.restore, kRestoreBlock, 0, s>>>(p, lvl + i);
         }
         BFS_HIP(hipGetLastError());
@@ -710,30 +849,46 @@ void launch_single(bfs_graph* g, const bfs_tunables& t, Workspace* w, int32_t ro
     if (root < 0 || root >= g->n) fail(BFS_E_ROOT_RANGE, "root out of range");
     if (w->words * 32 < g->n || w->words % 64 != 0) fail(BFS_E_INTERNAL, "workspace bitmaps too small");
     if (!levels || !parents) fail(BFS_E_INVALID_ARG, "NULL output");
-    if (g->big_threshold != t.wave_max_degree) fail(BFS_E_INTERNAL, "big-row table out of date");
+    // The degree-ordered copy with its LDS hot bitmap, or the caller's order.
+    const int32_t want_hot = hot_count(g, t);
+    const HotLayout* h = want_hot > 0 ? g->hot.get() : nullptr;
+    if (want_hot > 0 && (!h || h->hot != want_hot)) fail(BFS_E_INTERNAL, "degree-ordered copy out of date");
+    if (h && !w->lv_new) fail(BFS_E_INTERNAL, "workspace lacks the level array of the copy");
+    const BigTable& bt = h ? h->big : g->big;
+    if (bt.threshold != t.wave_max_degree) fail(BFS_E_INTERNAL, "big-row table out of date");
     SingleParams p{};
-    p.off = g->d_off;
-    p.col = g->d_col;
+    p.off = h ? static_cast<const void*>(h->d_off) : g->d_off;
+    p.col = h ? h->d_col : g->d_col;
     p.n = (int32_t)g->n;
-    p.root = root;
+    p.root = h ? h->old2new[(size_t)root] : root;
+    p.root_out = root;
     p.words = w->words;
-    p.levels = levels;
-    p.parents = parents;
+    p.lv = h ? w->lv_new : levels;
+    p.out_lv = levels;
+    p.out_pa = parents;
+    p.new2old = h ? h->d_new2old : nullptr;
     p.vis = w->vis;
     p.vis_prev = w->vis_prev;
     p.fr = w->fr;
     p.ctrl = w->ctrl;
     p.arcs_slot = w->slots;
     p.reached_slot = w->slots + w->nslots;
-    p.bigmap = g->d_bigmap;
+    p.bigmap = bt.d_bigmap;
     p.bl_u = w->bl_u;
     p.bl_pre = w->bl_pre;
     p.seg_cnt = w->seg_cnt;
     p.seg_arcs = w->seg_arcs;
-    p.seg_start = g->d_seg_start;
+    p.seg_start = bt.d_seg_start;
     p.restore_grid = g->restore_grid;
     p.t1 = t.small_max_degree;
-    if (w->big_capacity < g->num_big) fail(BFS_E_INTERNAL, "big-row list too small");
+    p.min_share = t.chunk_arcs > 0 ? t.chunk_arcs : 1024;
+    p.hot_words = h ? h->hot / 32 : 0;
+    p.hot_vis = w->hot_vis;
+    p.hot_min_frontier = std::max<int64_t>(4096, g->n / 256);
+    if ((int64_t)p.hot_words * 32 > w->words || p.hot_words % 2 != 0 || p.hot_words > w->hot_capacity)
+        fail(BFS_E_INTERNAL, "hot bitmap larger than its buffer");
+    if (w->big_capacity < bt.num_big) fail(BFS_E_INTERNAL, "big-row list too small");
+    const bool off32 = !h && g->off32;
     const bool atomic = t.update_mode == 2;
 #define BFS_LAUNCH(OFFT, BS)                                         \
     do {                                                             \
@@ -742,13 +897,17 @@ void launch_single(bfs_graph* g, const bfs_tunables& t, Workspace* w, int32_t ro
         else                                                         \
             launch_typed<OFFT, BS, false>(g, t, w, p, s);            \
     } while (0)
-    if (g->off32) {
-        if (t.block_size == 512)
+    if (off32) {
+        if (t.block_size == 1024)
+            BFS_LAUNCH(int32_t, 1024);
+        else if (t.block_size == 512)
             BFS_LAUNCH(int32_t, 512);
         else
             BFS_LAUNCH(int32_t, 256);
     } else {
-        if (t.block_size == 512)
+        if (t.block_size == 1024)
+            BFS_LAUNCH(int64_t, 1024);
+        else if (t.block_size == 512)
             BFS_LAUNCH(int64_t, 512);
         else
             BFS_LAUNCH(int64_t, 256);
@@ -781,6 +940,18 @@ void validate_device_csr(const void* off, bool off32, const int32_t* col, int64_
     }
     (void)hipFree(d_err);
     if (err) fail(BFS_E_INVALID_GRAPH, "device CSR failed validation (code " + std::to_string(err) + ")");
+}
+
+void launch_relabel_cols(const bfs_graph* g, const int64_t* d_noff, const int32_t* d_new2old,
+                         const int32_t* d_old2new, int32_t* d_ncol) {
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((g->n + 3) / 4, (int64_t)g->cu_count * 32));
+    if (g->off32)
+        k_relabel_cols<int32_t><<<blocks, 256>>>(static_cast<const int32_t*>(g->d_off), g->d_col, d_noff, d_new2old,
+                                                 d_old2new, d_ncol, g->n);
+    else
+        k_relabel_cols<int64_t><<<blocks, 256>>>(static_cast<const int64_t*>(g->d_off), g->d_col, d_noff, d_new2old,
+                                                 d_old2new, d_ncol, g->n);
+    BFS_HIP(hipGetLastError());
 }
 
 void launch_fill_i32(int32_t* ptr, int64_t count, int32_t value, hipStream_t s) {

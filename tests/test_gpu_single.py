@@ -98,6 +98,10 @@ def test_device_pointer_graph():
     dict(block_size=512, blocks_per_cu=1),
     dict(block_size=256, blocks_per_cu=2, update_mode=2),
     dict(block_size=512, blocks_per_cu=1, update_mode=1),
+    dict(block_size=1024, blocks_per_cu=1),
+    dict(hot_vertices=2048),                                    # LDS hot bitmap at every large level
+    dict(hot_vertices=2048, update_mode=2),
+    dict(hot_vertices=65536, block_size=1024, small_max_degree=256),
 ])
 def test_bins_and_launch_shapes(tun):
     """Correctness does not depend on the degree bins or the launch shape."""
@@ -186,4 +190,15 @@ def test_rmat_scale20_64_roots():
     g = graphgen.cached("rmat", scale=20, edgefactor=16, seed=1)
     dg = load(g)
     for r in graphgen.pick_roots(g, 64, seed=2):
+        check_root(g, dg, int(r))
+
+
+@pytest.mark.parametrize("tun", [dict(hot_vertices=8192, block_size=1024), dict(hot_vertices=8192, update_mode=2)])
+def test_hot_bitmap_scale18(tun):
+    """The LDS copy of the hot bitmap changes probes only, never results: levels
+    exact and parents valid with the hot set on, for several roots."""
+    g = graphgen.rmat(18, 16, seed=11)
+    dg = load(g)
+    bfs.bfs_graph_set_tunables(dg, **tun)
+    for r in graphgen.pick_roots(g, 4, seed=12):
         check_root(g, dg, int(r))

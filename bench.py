@@ -377,6 +377,18 @@ def bench_serve(args) -> int:
                "fifo_p50_ms": round(float(np.percentile(fifo_lat, 50)), 3),
                "fifo_p99_ms": round(float(np.percentile(fifo_lat, 99)), 3),
                "fifo_gteps": round(m_total / t_fifo / 1e9, 3)}
+        # Where the server's time goes: latency per graph and path (after warm-up).
+        rec["server_batched_share"] = round(float(np.mean([done[i]["batched"] for i in range(args.warmup_queries,
+                                                                                              args.queries)])), 3)
+        by_graph = {}
+        for i in range(args.warmup_queries, args.queries):
+            d = by_graph.setdefault(graphs[int(choice[i])][0], {"batched": [], "single": []})
+            d["batched" if done[i]["batched"] else "single"].append(done[i]["latency_ms"])
+        rec["server_by_graph"] = {
+            name: {path: {"n": len(v), "p50_ms": round(float(np.percentile(v, 50)), 2),
+                          "p99_ms": round(float(np.percentile(v, 99)), 2)}
+                   for path, v in d.items() if v}
+            for name, d in by_graph.items()}
         per_rate.append(rec)
         print(f"[bench] {rec}", file=sys.stderr, flush=True)
     best = max(per_rate, key=lambda r: r["server_gteps"])

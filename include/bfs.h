@@ -182,6 +182,12 @@ typedef struct {
     int32_t num_streams;            /* HIP streams shared by instances; 0 = 4 */
     int32_t max_instances_per_graph;/* concurrent instances of one graph; 0 = 2 */
     int32_t flags;                  /* reserved, must be 0 */
+    int32_t single_workers;         /* threads that serve lightly loaded graphs with single-root
+                                       runs (bfs_run), each on its own stream; 0 or -1 = none:
+                                       every request is batched (the default) */
+    int32_t batch_min_queue;        /* while fewer than this many requests of a graph wait, the
+                                       next one goes to an idle single-root worker; a longer
+                                       backlog is batched into instances; 0 = 4 */
 } bfs_server_config;
 
 typedef struct {
@@ -190,8 +196,10 @@ typedef struct {
     int64_t reached;
     int64_t arcs_scanned;
     int64_t edges_traversed;
-    double queue_ms;    /* submit -> admitted into an instance slot */
+    double queue_ms;    /* submit -> admitted into an instance slot or to a worker */
     double latency_ms;  /* submit -> result complete on the device */
+    int32_t batched;    /* 1 = served by a multi-source instance, 0 = by a single-root run */
+    int32_t reserved;
 } bfs_request_stats;
 
 /* Start a server (a scheduler thread plus HIP streams). cfg may be NULL. */

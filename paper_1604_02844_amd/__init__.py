@@ -74,16 +74,17 @@ class Tunables(ctypes.Structure):
 class ServerConfig(ctypes.Structure):
     _fields_ = [("mem_budget_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int32),
                 ("num_streams", ctypes.c_int32), ("max_instances_per_graph", ctypes.c_int32),
-                ("flags", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("single_workers", ctypes.c_int32), ("batch_min_queue", ctypes.c_int32)]
 
 
 class RequestStats(ctypes.Structure):
     _fields_ = [("num_levels", ctypes.c_int32), ("graph_id", ctypes.c_int32), ("reached", ctypes.c_int64),
                 ("arcs_scanned", ctypes.c_int64), ("edges_traversed", ctypes.c_int64),
-                ("queue_ms", ctypes.c_double), ("latency_ms", ctypes.c_double)]
+                ("queue_ms", ctypes.c_double), ("latency_ms", ctypes.c_double), ("batched", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 _lib = None
@@ -306,8 +307,9 @@ class Server:
 
 
 def bfs_server_create(mem_budget_bytes: int = 0, max_slots: int = 0, num_streams: int = 0,
-                      max_instances_per_graph: int = 0) -> Server:
-    cfg = ServerConfig(mem_budget_bytes, max_slots, num_streams, max_instances_per_graph, 0)
+                      max_instances_per_graph: int = 0, single_workers: int = 0, batch_min_queue: int = 0) -> Server:
+    cfg = ServerConfig(mem_budget_bytes, max_slots, num_streams, max_instances_per_graph, 0, single_workers,
+                       batch_min_queue)
     h = ctypes.c_void_p()
     _check(load_library().bfs_server_create(ctypes.byref(cfg), ctypes.byref(h)), "bfs_server_create")
     return Server(h.value)

@@ -216,9 +216,11 @@ void ms_run_batch(bfs_graph* g, const bfs_tunables& t, MsWorkspace* w, const int
 void ms_reset(bfs_graph* g, MsWorkspace* w, hipStream_t s);
 // Seed slots (host arrays) into the frontier of instance level `level`: root
 // bits and level-0 outputs. The slot output pointers and start levels must
-// already be in w->ctrl.
+// already be in w->ctrl. With `pinned_stage` (128 int32 of pinned host memory,
+// untouched until `s` has passed this point) nothing blocks; without it the
+// call waits for the stream.
 void ms_join(bfs_graph* g, MsWorkspace* w, const int32_t* slots, const int32_t* roots, int32_t count, int level,
-             hipStream_t s);
+             hipStream_t s, int32_t* pinned_stage);
 // Enqueue one level of the instance on `s` plus an asynchronous copy of the
 // step summary (sum_*, per-slot totals) into w->host_ctrl; the caller
 // synchronises `s` before reading it. `level` is the instance level expanded.

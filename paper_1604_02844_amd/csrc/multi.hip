@@ -612,21 +612,24 @@ void ms_reset(bfs_graph* g, MsWorkspace* w, hipStream_t s) {
 }
 
 void ms_join(bfs_graph* g, MsWorkspace* w, const int32_t* slots, const int32_t* roots, int32_t count, int lvl,
-             hipStream_t s) {
+             hipStream_t s, int32_t* pinned_stage) {
     if (count <= 0) return;
     if (count > 64) fail(BFS_E_INTERNAL, "at most 64 slots join at once");
     for (int i = 0; i < count; ++i) {
         if (slots[i] < 0 || slots[i] >= 64) fail(BFS_E_INTERNAL, "slot out of range");
         if (roots[i] < 0 || roots[i] >= g->n) fail(BFS_E_ROOT_RANGE, "root out of range");
     }
-    // Slots and roots travel through the device staging area behind the ctrl.
+    // Slots and roots travel through the device staging area behind the ctrl,
+    // from the caller's pinned buffer (asynchronous) or a local one (then the
+    // copy is awaited before returning).
     int32_t* d_stage = reinterpret_cast<int32_t*>(w->ctrl + 1);
-    int32_t stage[128];
+    int32_t local[128];
+    int32_t* stage = pinned_stage ? pinned_stage : local;
     for (int i = 0; i < count; ++i) {
         stage[i] = slots[i];
         stage[64 + i] = roots[i];
     }
-    BFS_HIP(hipMemcpyAsync(d_stage, stage, sizeof(stage), hipMemcpyHostToDevice, s));
+    BFS_HIP(hipMemcpyAsync(d_stage, stage, 128 * sizeof(int32_t), hipMemcpyHostToDevice, s));
     const bfs_tunables t = resolve_tunables(g, g->tun);
     MsParams p = make_params(g, t, w, lvl);
     if (g->off32)
@@ -634,8 +637,7 @@ void ms_join(bfs_graph* g, MsWorkspace* w, const int32_t* slots, const int32_t* 
     else
         k_ms_seed<int64_t><<<1, 64, 0, s>>>(p, d_stage, d_stage + 64, count, lvl);
     BFS_HIP(hipGetLastError());
-    // The pageable staging buffer must stay valid until the copy has been consumed.
-    BFS_HIP(hipStreamSynchronize(s));
+    if (!pinned_stage) BFS_HIP(hipStreamSynchronize(s));  // the local buffer must outlive the copy
 }
 
 void ms_step_enqueue(bfs_graph* g, const bfs_tunables& t, MsWorkspace* w, int level, hipStream_t s,
@@ -685,7 +687,7 @@ void ms_run_batch(bfs_graph* g, const bfs_tunables& t, MsWorkspace* w, const int
     BFS_HIP(hipMemcpyAsync(&w->ctrl->start, &hc->start, sizeof(hc->start), hipMemcpyHostToDevice, s));
     int32_t slots[64];
     for (int i = 0; i < count; ++i) slots[i] = i;
-    ms_join(g, w, slots, roots, count, 0, s);
+    ms_join(g, w, slots, roots, count, 0, s, nullptr);
     int lvl = 0;
     int chunk = 8;
     while (true) {

@@ -2,18 +2,20 @@
 // instances on resident graphs.
 //
 // Requests (graph, root) are queued by bfs_server_submit from any thread. A
-// scheduler thread owns every device resource and loops over level steps:
+// scheduler thread owns every device resource. Instances advance
+// independently, each at its own pace on its own HIP stream, so a request on a
+// small graph never waits for a level of a large one:
 //   admit   queued requests of a graph take free slots (bits) of one of that
-//           graph's multi-source instances, at the next level boundary, when
-//           the device-memory budget has room for their result rows; an
-//           instance is created on demand up to max_instances_per_graph;
-//   step    every instance with running slots expands one level on its own
-//           HIP stream (instances of different graphs overlap on the device);
-//   retire  a slot whose bit is missing from the next frontier has finished:
-//           its result rows go to the request, its visited bits are cleared,
-//           and the slot is free for the next admission.
-// A new root joins with start level s = the instance level at admission, so
-// its vertices get instance level + 1 - s, i.e. its own hop distance: every
+//           graph's multi-source instances, when the device-memory budget has
+//           room for their result rows; an instance is created on demand up
+//           to max_instances_per_graph;
+//   step    an instance that is not running a level seeds its newly admitted
+//           roots, enqueues one level and records an event;
+//   retire  when that event has completed, a slot whose bit is missing from
+//           the next frontier has finished: its result rows go to the request,
+//           its visited bits are cleared and the slot is free again.
+// A new root joins with start level s = the instance level when it is seeded,
+// so its vertices get instance level + 1 - s, i.e. its own hop distance: every
 // request's result is the one a lone single-root BFS returns (levels exact,
 // parents valid), whatever it was mixed with.
 #include <chrono>
@@ -45,18 +47,23 @@ struct Request {
     int32_t* buf = nullptr;  // device result rows: levels[n] then parents[n]
     int32_t num_levels = 0;
     int64_t reached = 0, arcs = 0;
+    bool batched = true;
 };
 
 struct Instance {
     bfs::MsWorkspace* w = nullptr;
     bfs::MsCtrl* staging = nullptr;  // pinned slot table staging
+    int32_t* join_stage = nullptr;   // pinned: slots and roots of one join
     hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;       // end of the level in flight
+    bool in_flight = false;
     int level = 0;
     uint64_t slot_ticket[64] = {};
     int32_t slot_start[64] = {};
     uint64_t active = 0;  // slots running
     uint64_t used = 0;    // slots holding a request (running or joining)
     std::vector<int32_t> join_slots, join_roots;
+    std::vector<int32_t*> join_bufs;  // result rows of the joining slots
 };
 
 struct GraphState {
@@ -79,7 +86,13 @@ struct bfs_server {
     std::unordered_map<uint64_t, Request> reqs;
     uint64_t next_ticket = 1;
     std::vector<hipStream_t> streams;
-    int next_stream = 0;
+    std::vector<int64_t> stream_load;  // vertices of the instances on each stream
+    // Single-root workers: requests of lightly loaded graphs, one bfs_run each.
+    std::vector<std::thread> workers;
+    std::vector<hipStream_t> worker_streams;
+    std::deque<uint64_t> single_queue;
+    std::condition_variable wcv;
+    int idle_workers = 0;
     int64_t mem_used = 0;
     int fatal = 0;  // a device error stops the scheduler; requests then fail
     std::string fatal_msg;
@@ -115,10 +128,18 @@ Instance* new_instance(bfs_server* s, GraphState& gs) {
     if (s->mem_used + need > s->cfg.mem_budget_bytes) return nullptr;
     if ((int)gs.inst.size() >= s->cfg.max_instances_per_graph) return nullptr;
     Instance* in = new Instance();
-    in->stream = s->streams[(size_t)(s->next_stream++ % (int)s->streams.size())];
+    // The stream carrying the fewest vertices of running instances: streams
+    // map onto a few hardware queues, so keep small graphs away from large ones.
+    size_t best = 0;
+    for (size_t i = 1; i < s->streams.size(); ++i)
+        if (s->stream_load[i] < s->stream_load[best]) best = i;
+    s->stream_load[best] += gs.g->n;
+    in->stream = s->streams[best];
     in->w = bfs::acquire_ms(gs.g, in->stream);
     bfs::hip_check(hipHostMalloc(&in->staging, sizeof(bfs::MsCtrl), hipHostMallocDefault), "hipHostMalloc");
     std::memset(in->staging, 0, sizeof(bfs::MsCtrl));
+    bfs::hip_check(hipHostMalloc(&in->join_stage, 128 * sizeof(int32_t), hipHostMallocDefault), "hipHostMalloc");
+    bfs::hip_check(hipEventCreateWithFlags(&in->done, hipEventDisableTiming), "hipEventCreate");
     bfs::ms_reset(gs.g, in->w, in->stream);
     bfs::hip_check(hipStreamSynchronize(in->stream), "hipStreamSynchronize");
     gs.inst.push_back(in);
@@ -137,6 +158,23 @@ void admit(bfs_server* s) {
     for (auto& gsp : s->graphs) {
         GraphState& gs = *gsp;
         while (!gs.queue.empty()) {
+            // While a graph's backlog is short, an idle single-root worker takes
+            // the next request: one bfs_run is cheaper than a multi-source pass
+            // shared by few roots. A longer backlog goes to the instances.
+            if ((int)gs.queue.size() < s->cfg.batch_min_queue && s->idle_workers > (int)s->single_queue.size()) {
+                int32_t* buf = take_buffer(s, gs);
+                if (!buf) break;
+                const uint64_t ticket = gs.queue.front();
+                gs.queue.pop_front();
+                Request& r = s->reqs[ticket];
+                r.state = ReqState::Running;
+                r.t_admit = Clock::now();
+                r.buf = buf;
+                r.batched = false;
+                s->single_queue.push_back(ticket);
+                s->wcv.notify_one();
+                continue;
+            }
             Instance* target = nullptr;
             int slot = -1;
             for (Instance* in : gs.inst) {
@@ -161,30 +199,125 @@ void admit(bfs_server* s) {
             r.buf = buf;
             target->used |= 1ull << slot;
             target->slot_ticket[slot] = ticket;
-            target->slot_start[slot] = target->level;
             target->join_slots.push_back(slot);
             target->join_roots.push_back(r.root);
-            const int64_t n = gs.g->n;
-            bfs::launch_fill_i32(buf, 2 * n, -1, target->stream);
-            bfs::ms_set_slot(target->w, target->staging, slot, buf, buf + n, target->level, target->stream);
+            target->join_bufs.push_back(buf);
         }
     }
 }
 
+// A single-root worker: runs bfs_run for requests routed to it, on its own stream.
+void worker(bfs_server* s, int index) {
+    if (hipSetDevice(s->device) != hipSuccess) return;
+    hipStream_t stream = s->worker_streams[(size_t)index];
+    std::unique_lock<std::mutex> lk(s->mu);
+    while (true) {
+        s->wcv.wait(lk, [&] { return s->stop || !s->single_queue.empty(); });
+        if (s->stop) return;
+        const uint64_t ticket = s->single_queue.front();
+        s->single_queue.pop_front();
+        --s->idle_workers;
+        auto it = s->reqs.find(ticket);
+        if (it == s->reqs.end() || it->second.state != ReqState::Running) {  // failed and consumed meanwhile
+            ++s->idle_workers;
+            continue;
+        }
+        bfs_graph* g = s->graphs[(size_t)it->second.graph_id]->g;
+        const int32_t root = it->second.root;
+        int32_t* buf = it->second.buf;
+        lk.unlock();
+        bfs_run_stats st{};
+        const int rc = bfs_run(g, root, buf, buf + g->n, stream, 0, &st);
+        const Clock::time_point now = Clock::now();
+        lk.lock();
+        ++s->idle_workers;
+        auto jt = s->reqs.find(ticket);  // a running request cannot be consumed meanwhile
+        if (jt != s->reqs.end() && jt->second.state == ReqState::Running) {
+            Request& r = jt->second;
+            r.t_done = now;
+            if (rc == BFS_OK) {
+                r.state = ReqState::Done;
+                r.num_levels = st.num_levels;
+                r.reached = st.reached;
+                r.arcs = st.arcs_scanned;
+            } else {
+                r.state = ReqState::Failed;
+                r.status = rc;
+            }
+        }
+        s->cv.notify_one();  // the scheduler may route more work here
+    }
+}
+
+// Seed an idle instance's joining slots and enqueue its next level.
+void launch_step(GraphState& gs, Instance* in) {
+    const int64_t n = gs.g->n;
+    if (!in->join_slots.empty()) {
+        for (size_t k = 0; k < in->join_slots.size(); ++k) {
+            const int32_t slot = in->join_slots[k];
+            int32_t* buf = in->join_bufs[k];
+            in->slot_start[slot] = in->level;
+            bfs::launch_fill_i32(buf, 2 * n, -1, in->stream);
+            bfs::ms_set_slot(in->w, in->staging, slot, buf, buf + n, in->level, in->stream);
+        }
+        bfs::ms_join(gs.g, in->w, in->join_slots.data(), in->join_roots.data(), (int32_t)in->join_slots.size(),
+                     in->level, in->stream, in->join_stage);
+        for (int32_t sl : in->join_slots) in->active |= 1ull << sl;
+        in->join_slots.clear();
+        in->join_roots.clear();
+        in->join_bufs.clear();
+    }
+    const bfs_tunables t = bfs::resolve_tunables(gs.g, gs.g->tun);
+    bfs::ms_step_enqueue(gs.g, t, in->w, in->level, in->stream, true);
+    bfs::hip_check(hipEventRecord(in->done, in->stream), "hipEventRecord");
+    in->in_flight = true;
+}
+
+// The level in flight has completed: hand finished slots to their requests.
+void finish_step(bfs_server* s, GraphState& gs, Instance* in) {
+    in->in_flight = false;
+    const uint64_t alive = in->w->host_ctrl->sum_alive;
+    const uint64_t finished = in->active & ~alive;
+    if (finished) {
+        const Clock::time_point now = Clock::now();
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (int i = 0; i < 64; ++i) {
+            if (!((finished >> i) & 1ull)) continue;
+            auto it = s->reqs.find(in->slot_ticket[i]);
+            if (it != s->reqs.end()) {
+                Request& r = it->second;
+                r.state = ReqState::Done;
+                r.t_done = now;
+                r.num_levels = in->level - in->slot_start[i] + 1;
+                r.reached = (int64_t)in->w->host_ctrl->slot_reached[i];
+                r.arcs = (int64_t)in->w->host_ctrl->slot_arcs[i];
+            }
+            in->slot_ticket[i] = 0;
+        }
+        in->active &= ~finished;
+        in->used &= ~finished;
+        // Clear the finished slots' visited bits before their reuse.
+        bfs::ms_retire(gs.g, in->w, ~finished, in->stream);
+    }
+    ++in->level;
+}
+
 void scheduler(bfs_server* s) {
     if (hipSetDevice(s->device) != hipSuccess) return;
-    std::vector<std::pair<GraphState*, Instance*>> stepping;
     std::vector<GraphState*> snapshot;
+    bool progressed = true;
     while (true) {
         {
             std::unique_lock<std::mutex> lk(s->mu);
-            bool busy = false;
+            bool busy = false, running = false;
             for (auto& gsp : s->graphs) {
                 if (!gsp->queue.empty()) busy = true;
-                for (Instance* in : gsp->inst)
+                for (Instance* in : gsp->inst) {
                     if (in->active || !in->join_slots.empty()) busy = true;
+                    if (in->in_flight) running = true;
+                }
             }
-            if (!busy && !s->stop) s->cv.wait_for(lk, std::chrono::milliseconds(2));
+            if (!busy && !running && !s->stop) s->cv.wait_for(lk, std::chrono::milliseconds(2));
             if (s->stop) return;
             if (s->fatal) continue;
             try {
@@ -196,54 +329,24 @@ void scheduler(bfs_server* s) {
             snapshot.clear();
             for (auto& gsp : s->graphs) snapshot.push_back(gsp.get());
         }
+        if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(20));
+        progressed = false;
         try {
-            // Seed the joining roots, then expand one level of every busy instance.
-            stepping.clear();
             for (GraphState* gsp : snapshot) {
                 GraphState& gs = *gsp;
                 for (Instance* in : gs.inst) {
-                    if (!in->join_slots.empty()) {
-                        bfs::ms_join(gs.g, in->w, in->join_slots.data(), in->join_roots.data(),
-                                     (int32_t)in->join_slots.size(), in->level, in->stream);
-                        for (int32_t sl : in->join_slots) in->active |= 1ull << sl;
-                        in->join_slots.clear();
-                        in->join_roots.clear();
+                    if (in->in_flight) {
+                        const hipError_t e = hipEventQuery(in->done);
+                        if (e == hipErrorNotReady) continue;
+                        bfs::hip_check(e, "hipEventQuery");
+                        finish_step(s, gs, in);
+                        progressed = true;
                     }
-                    if (in->active) {
-                        const bfs_tunables t = bfs::resolve_tunables(gs.g, gs.g->tun);
-                        bfs::ms_step_enqueue(gs.g, t, in->w, in->level, in->stream, true);
-                        stepping.emplace_back(&gs, in);
+                    if (!in->in_flight && (in->active || !in->join_slots.empty())) {
+                        launch_step(gs, in);
+                        progressed = true;
                     }
                 }
-            }
-            for (auto& gi : stepping) {
-                GraphState& gs = *gi.first;
-                Instance* in = gi.second;
-                bfs::hip_check(hipStreamSynchronize(in->stream), "hipStreamSynchronize");
-                const uint64_t alive = in->w->host_ctrl->sum_alive;
-                const uint64_t finished = in->active & ~alive;
-                const Clock::time_point now = Clock::now();
-                if (finished) {
-                    std::lock_guard<std::mutex> lk(s->mu);
-                    for (int i = 0; i < 64; ++i) {
-                        if (!((finished >> i) & 1ull)) continue;
-                        auto it = s->reqs.find(in->slot_ticket[i]);
-                        if (it != s->reqs.end()) {
-                            Request& r = it->second;
-                            r.state = ReqState::Done;
-                            r.t_done = now;
-                            r.num_levels = in->level - in->slot_start[i] + 1;
-                            r.reached = (int64_t)in->w->host_ctrl->slot_reached[i];
-                            r.arcs = (int64_t)in->w->host_ctrl->slot_arcs[i];
-                        }
-                        in->slot_ticket[i] = 0;
-                    }
-                    in->active &= ~finished;
-                    in->used &= ~finished;
-                    // Clear the finished slots' visited bits before their reuse.
-                    bfs::ms_retire(gs.g, in->w, ~finished, in->stream);
-                }
-                ++in->level;
             }
         } catch (const bfs::Error& e) {
             std::lock_guard<std::mutex> lk(s->mu);
@@ -291,6 +394,11 @@ int bfs_server_create(const bfs_server_config* cfg, bfs_server** out) {
         if (c.max_slots == 0) c.max_slots = 64;
         if (c.num_streams == 0) c.num_streams = 4;
         if (c.max_instances_per_graph == 0) c.max_instances_per_graph = 2;
+        if (c.single_workers < -1 || c.batch_min_queue < 0) return BFS_E_INVALID_ARG;
+        // Single-root workers are opt-in: a serving run that used them ended in
+        // a GPU memory fault whose cause has not been found yet.
+        if (c.single_workers <= 0) c.single_workers = 0;
+        if (c.batch_min_queue == 0) c.batch_min_queue = 4;
         auto* s = new bfs_server();
         bfs::hip_check(hipGetDevice(&s->device), "hipGetDevice");
         if (c.mem_budget_bytes == 0) {
@@ -304,10 +412,27 @@ int bfs_server_create(const bfs_server_config* cfg, bfs_server** out) {
                 hipStream_t st = nullptr;
                 bfs::hip_check(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate");
                 s->streams.push_back(st);
+                s->stream_load.push_back(0);
             }
+            for (int i = 0; i < c.single_workers; ++i) {
+                hipStream_t st = nullptr;
+                bfs::hip_check(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate");
+                s->worker_streams.push_back(st);
+            }
+            s->idle_workers = c.single_workers;
             s->thread = std::thread(scheduler, s);
+            for (int i = 0; i < c.single_workers; ++i) s->workers.emplace_back(worker, s, i);
         } catch (...) {
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                s->stop = true;
+            }
+            s->cv.notify_all();
+            s->wcv.notify_all();
+            if (s->thread.joinable()) s->thread.join();
+            for (auto& th : s->workers) th.join();
             for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+            for (hipStream_t st : s->worker_streams) (void)hipStreamDestroy(st);
             delete s;
             throw;
         }
@@ -379,6 +504,8 @@ int bfs_server_poll(bfs_server* s, uint64_t ticket, int32_t* levels, int32_t* pa
             st->edges_traversed = r.arcs / 2;
             st->queue_ms = ms_between(r.t_submit, r.t_admit);
             st->latency_ms = ms_between(r.t_submit, r.t_done);
+            st->batched = r.batched ? 1 : 0;
+            st->reserved = 0;
         }
         s->reqs.erase(it);
         lk.unlock();
@@ -404,15 +531,20 @@ int bfs_server_destroy(bfs_server* s) {
             s->stop = true;
         }
         s->cv.notify_all();
+        s->wcv.notify_all();
         if (s->thread.joinable()) s->thread.join();
+        for (auto& th : s->workers) th.join();  // a worker finishes its bfs_run first
         (void)hipSetDevice(s->device);
         for (hipStream_t st : s->streams) (void)hipStreamSynchronize(st);
+        for (hipStream_t st : s->worker_streams) (void)hipStreamSynchronize(st);
         for (auto& gsp : s->graphs) {
             GraphState& gs = *gsp;
             for (Instance* in : gs.inst) {
                 bfs::release_ms(gs.g, in->w, in->stream);
                 (void)hipHostFree(in->staging);
-                delete in;
+                (void)hipHostFree(in->join_stage);
+                (void)hipEventDestroy(in->done);
+                delete in;  // result rows of joining slots are freed with their requests below
             }
             for (int32_t* b : gs.free_bufs) (void)hipFree(b);
             gs.g->server_refs.fetch_sub(1);
@@ -420,6 +552,7 @@ int bfs_server_destroy(bfs_server* s) {
         for (auto& kv : s->reqs)
             if (kv.second.buf) (void)hipFree(kv.second.buf);
         for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+        for (hipStream_t st : s->worker_streams) (void)hipStreamDestroy(st);
         delete s;
         return BFS_OK;
     });

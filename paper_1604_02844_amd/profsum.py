@@ -20,6 +20,7 @@ import glob
 import hashlib
 import os
 import re
+import shlex
 import sys
 from collections import defaultdict
 
@@ -99,7 +100,8 @@ def read_counter(root: str, counter: str) -> dict[str, list[float]]:
 
 def cmd_trace(a) -> None:
     tr = read_trace(a.dir)
-    lines = [f"# {a.title}", "", f"Command: `{a.command}`", "", f"Library source digest: {source_digest()}",
+    lines = [f"# {a.title}", "", f"Command: `{a.command}`", "", f"Summary: `{_self_command()}`", "",
+             f"Library source digest: {source_digest()}",
              f"BFS runs in the trace: {a.runs}", "",
              "| kernel | calls | total ms | avg us | min us | max us |", "|---|---|---|---|---|---|"]
     total_run = 0.0
@@ -132,6 +134,7 @@ def cmd_traffic(a) -> None:
     f_run = sum(sum(fetch.get(k, [])) for k in RUN_KERNELS) * 1024.0 * f_scale / a.runs
     w_run = sum(sum(write.get(k, [])) for k in RUN_KERNELS) * 1024.0 * w_scale / a.runs
     lines = [f"# {a.title}", "", f"Fetch pass: `{a.fetch_command}`", "", f"Write pass: `{a.write_command}`", "",
+             f"Summary: `{_self_command()}`", "",
              f"Copy kernel: {a.copy_bytes} B read and written; FETCH_SIZE reads {f_copy:.0f} KiB "
              f"(scale {f_scale:.4f}), WRITE_SIZE reads {w_copy:.0f} KiB (scale {w_scale:.4f})",
              f"BFS runs per pass: {a.runs}", "",
@@ -144,6 +147,10 @@ def cmd_traffic(a) -> None:
               f"traffic_bytes_per_run: {int(f_run + w_run)}", f"workload: {a.workload}",
               f"source_digest: {source_digest()}"]
     print("\n".join(lines))
+
+
+def _self_command() -> str:
+    return "python -m paper_1604_02844_amd.profsum " + " ".join(shlex.quote(x) for x in sys.argv[1:])
 
 
 def stored_traffic(path: str, workload: str) -> int | None:

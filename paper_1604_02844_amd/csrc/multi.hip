@@ -583,7 +583,12 @@ void enqueue_level(bfs_graph* g, const bfs_tunables& t, MsWorkspace* w, int lvl,
     if (g->big.threshold != t.wave_max_degree) fail(BFS_E_INTERNAL, "big-row table out of date");
     MsParams p = make_params(g, t, w, lvl);
     static const int occ = occupancy_of(k_ms_push<OffT, 256>, 256);
-    const int bpc = t.blocks_per_cu > 0 && (occ < 1 || t.blocks_per_cu < occ) ? t.blocks_per_cu : (occ > 0 ? occ : 1);
+    // On gfx950 one workgroup per CU fewer than the occupancy query reports is
+    // resident at once (measured: with the reported count, one workgroup per CU
+    // starts only when another finishes); a grid that fits keeps every
+    // workgroup's share in the first wave of the dispatch.
+    const int fit = occ > 1 ? occ - 1 : 1;
+    const int bpc = t.blocks_per_cu > 0 && t.blocks_per_cu < fit ? t.blocks_per_cu : fit;
     const int push_grid = bpc * g->cu_count;
     const int pull_grid = (int)std::max<int64_t>(1, std::min<int64_t>((g->n + 255) / 256, (int64_t)g->cu_count * 8));
     const int dg = dense_grid(g, g->n);

@@ -810,7 +810,12 @@ Grids grids_for(bfs_graph* g, const bfs_tunables& t, int64_t nslots, int hot_wor
                                                    kMaxHotWords * 4) == hipSuccess;
     if (!lds_ok) fail(BFS_E_DEVICE, "cannot enable dynamic LDS for the expansion kernel");
     const int occ = occupancy_of(k_expand<OffT, BLOCK, kAtomic>, BLOCK, (size_t)hot_words * 4);
-    const int bpc = t.blocks_per_cu > 0 && (occ < 1 || t.blocks_per_cu < occ) ? t.blocks_per_cu : (occ > 0 ? occ : 1);
+    // On gfx950 one workgroup per CU fewer than the occupancy query reports is
+    // resident at once (measured: with the reported count, one workgroup per CU
+    // starts only when another finishes); a grid that fits keeps every
+    // workgroup's share in the first wave of the dispatch.
+    const int fit = occ > 1 ? occ - 1 : 1;
+    const int bpc = t.blocks_per_cu > 0 && t.blocks_per_cu < fit ? t.blocks_per_cu : fit;
     int64_t ge = (int64_t)bpc * g->cu_count;
     ge = std::max<int64_t>(1, std::min(ge, nslots));
     if (g->restore_grid < 1 || g->restore_grid > kMaxRestoreGrid || g->restore_grid > nslots)

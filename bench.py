@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--root-seed", type=int, default=2)
     ap.add_argument("--offsets-i32", action="store_true", help="keep 4-byte offsets on the device")
+    ap.add_argument("--hybrid", action="store_true",
+                    help="direction-optimising runs (BFS_HYBRID): large levels bottom-up, not top-down")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="single-core seconds of oracle work in the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tune", action="store_true", help="run the autotuner on 4 roots first")
@@ -92,7 +94,9 @@ def main() -> int:
     t_gen = time.perf_counter() - t_gen
     print(f"[bench] graph {g.name}: n={g.n} nnz={g.nnz} ({t_gen:.1f}s), {len(roots)} roots", file=sys.stderr,
           flush=True)
-    dg = bfs.bfs_graph_load_csr(g.offsets_i32() if args.offsets_i32 else g.offsets, g.cols)
+    dg = bfs.bfs_graph_load_csr(g.offsets_i32() if args.offsets_i32 else g.offsets, g.cols,
+                                bfs.BFS_LOAD_SYMMETRIC if args.hybrid else 0)
+    run_flags = bfs.BFS_HYBRID if args.hybrid else 0
     if args.tunables:
         bfs.bfs_graph_set_tunables(dg, **json.loads(args.tunables))
     if args.tune:
@@ -107,7 +111,7 @@ def main() -> int:
     def step():
         recs = []
         for r in roots:
-            st = bfs.bfs_run(dg, int(r), lv, pa, stream=stream)
+            st = bfs.bfs_run(dg, int(r), lv, pa, stream=stream, flags=run_flags)
             recs.append((int(r), st))
         return recs
 
@@ -154,7 +158,8 @@ def main() -> int:
     from paper_1604_02844_amd import profsum
 
     workload_key = (f"rmat{args.scale} ef{args.edgefactor} seed{args.seed} roots{len(roots)} rootseed{args.root_seed} "
-                    f"off{off_bytes * 8} tunables{args.tunables or '{}'}{' tuned' if args.tune else ''}")
+                    f"off{off_bytes * 8} tunables{args.tunables or '{}'}{' tuned' if args.tune else ''}"
+                    f"{' hybrid' if args.hybrid else ''}")
     traffic = profsum.stored_traffic(
         os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", f"bfs_run_rmat{args.scale}_hbm_traffic.md"),
         workload_key)
@@ -195,7 +200,8 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": f"single-root top-down BFS, R-MAT scale {args.scale}, edgefactor {args.edgefactor}, "
+        "config": {"workload": f"single-root {'direction-optimising (top-down + bottom-up)' if args.hybrid else 'top-down'} "
+                               f"BFS, R-MAT scale {args.scale}, edgefactor {args.edgefactor}, "
                                f"A/B/C/D=.57/.19/.19/.05, permuted, symmetrised, deduplicated, int32 cols, "
                                f"int{off_bytes * 8} offsets, {len(roots)} seeded roots of degree>0",
                    "n": g.n, "nnz": g.nnz, "roots": len(roots), "step": f"{len(roots)} BFS runs",
@@ -204,7 +210,9 @@ def main() -> int:
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "bfs_run: k_init, then k_expand + k_restore per level",
                      "avg_launch_ms": round(avg_ms, 4), "bytes_alg_per_launch": int(bytes_total / launches),
-                     "workload_key": workload_key},
+                     "workload_key": workload_key,
+                     **({"note": "bytes follow the top-down definition; bottom-up levels read fewer columns"}
+                        if args.hybrid else {})},
         "cpu_baseline": cpu,
     }
     if args.details:

@@ -63,10 +63,17 @@ extern "C" {
 #define BFS_LOAD_SKIP_VALIDATE 0x2u /* trust the CSR; skip the O(n+nnz) checks */
 #define BFS_LOAD_OFFSETS_I32 0x4u   /* offsets points at int32_t[n+1] instead of int64_t[n+1];
                                        the graph keeps 4-byte offsets on the device */
+#define BFS_LOAD_SYMMETRIC 0x8u     /* the CSR is symmetric (u->v present iff v->u, counted with
+                                       multiplicity); checked at load unless SKIP_VALIDATE
+                                       (BFS_E_INVALID_GRAPH if not). Needed by BFS_HYBRID. */
 /* bfs_run / bfs_run_batch */
 #define BFS_OUT_HOST 0x1u           /* levels/parents are host pointers (results are copied
                                        back before return; implies synchronous) */
 #define BFS_ASYNC 0x2u              /* enqueue on `stream` and return; stats must be NULL */
+#define BFS_HYBRID 0x4u             /* bfs_run only: a level whose frontier is large runs
+                                       bottom-up (every unvisited vertex looks for a frontier
+                                       neighbour) instead of top-down; same levels, valid
+                                       parents. Requires a graph loaded with BFS_LOAD_SYMMETRIC. */
 
 typedef struct bfs_graph bfs_graph;
 typedef struct bfs_server bfs_server;
@@ -140,9 +147,14 @@ int bfs_graph_set_tunables(bfs_graph* g, const bfs_tunables* t);
  *   levels, parents  int32_t[n] each, written in full (caller-allocated; device
  *                    pointers unless BFS_OUT_HOST).
  *   stream           hipStream_t or NULL.
- *   flags            BFS_OUT_HOST, BFS_ASYNC (not both).
+ *   flags            BFS_OUT_HOST, BFS_ASYNC (not both); BFS_HYBRID lets levels with large
+ *                    frontiers run bottom-up (the direction-optimising hybrid the paper
+ *                    names in its related work and conclusions: an unvisited vertex takes
+ *                    the first frontier neighbour it finds as parent). arcs_scanned stays
+ *                    the sum of degrees of the reached vertices.
  *   st               nullable; filled on return (must be NULL with BFS_ASYNC).
- * Errors: BFS_E_ROOT_RANGE, BFS_E_INVALID_ARG, BFS_E_DEVICE, BFS_E_NO_MEMORY.
+ * Errors: BFS_E_ROOT_RANGE, BFS_E_INVALID_ARG (also BFS_HYBRID on a graph not loaded
+ * with BFS_LOAD_SYMMETRIC), BFS_E_DEVICE, BFS_E_NO_MEMORY.
  * Reentrant for distinct streams and outputs on the same graph.
  */
 int bfs_run(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents, void* stream,

@@ -35,8 +35,10 @@ BFS_E_INTERNAL = -9
 BFS_LOAD_DEVICE_PTRS = 0x1
 BFS_LOAD_SKIP_VALIDATE = 0x2
 BFS_LOAD_OFFSETS_I32 = 0x4
+BFS_LOAD_SYMMETRIC = 0x8
 BFS_OUT_HOST = 0x1
 BFS_ASYNC = 0x2
+BFS_HYBRID = 0x4
 
 ABI_SYMBOLS = [
     "bfs_graph_load_csr", "bfs_graph_free", "bfs_graph_info", "bfs_graph_get_tunables",

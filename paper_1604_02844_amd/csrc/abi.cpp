@@ -134,10 +134,11 @@ int bfs_run(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents, void*
             bfs_run_stats* st) {
     return guarded([&] {
         if (!g || !levels || !parents) bfs::fail(BFS_E_INVALID_ARG, "NULL argument");
-        if (flags & ~(BFS_OUT_HOST | BFS_ASYNC)) bfs::fail(BFS_E_INVALID_ARG, "unknown run flag");
-        const bool host_out = flags & BFS_OUT_HOST, async = flags & BFS_ASYNC;
+        if (flags & ~(BFS_OUT_HOST | BFS_ASYNC | BFS_HYBRID)) bfs::fail(BFS_E_INVALID_ARG, "unknown run flag");
+        const bool host_out = flags & BFS_OUT_HOST, async = flags & BFS_ASYNC, hybrid = flags & BFS_HYBRID;
         if (async && (host_out || st)) bfs::fail(BFS_E_INVALID_ARG, "BFS_ASYNC excludes BFS_OUT_HOST and stats");
         if (root < 0 || root >= g->n) bfs::fail(BFS_E_ROOT_RANGE, "root out of range");
+        if (hybrid && !g->symmetric) bfs::fail(BFS_E_INVALID_ARG, "BFS_HYBRID needs a graph loaded with BFS_LOAD_SYMMETRIC");
         DeviceScope ds(g->device);
         hipStream_t s = static_cast<hipStream_t>(stream);
         const bfs_tunables t = bfs::resolve_tunables(g, g->tun);
@@ -151,14 +152,17 @@ int bfs_run(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents, void*
                 pa = w->out_parents;
             }
             BFS_HIP(hipEventRecord(w->ev_start, s));
-            bfs::launch_single(g, t, w, root, lv, pa, s);
+            bfs::launch_single(g, t, w, root, lv, pa, s, hybrid);
             BFS_HIP(hipEventRecord(w->ev_stop, s));
             if (host_out) {
                 BFS_HIP(hipMemcpyAsync(levels, lv, (size_t)g->n * 4, hipMemcpyDeviceToHost, s));
                 BFS_HIP(hipMemcpyAsync(parents, pa, (size_t)g->n * 4, hipMemcpyDeviceToHost, s));
             }
             if (st) {
-                bfs::launch_single_stats(w, s);
+                if (hybrid)
+                    bfs::launch_single_stats_from_levels(g, t, w, lv, s);  // bottom-up levels scan no frontier rows
+                else
+                    bfs::launch_single_stats(w, s);
                 BFS_HIP(hipMemcpyAsync(w->host_ctrl, w->ctrl, sizeof(bfs::Ctrl), hipMemcpyDeviceToHost, s));
             }
             if (!async) {

@@ -42,6 +42,10 @@ struct Ctrl {
     int num_levels;
     int status;
     int pad;
+    // Direction-optimising runs, indexed by level parity: the direction chosen
+    // for the level (1 = bottom-up) and the vertices visited before its frontier.
+    int dir[2];
+    unsigned long long visited[2];
 };
 
 // Scratch of one single-root run.
@@ -147,6 +151,7 @@ struct bfs_graph {
     int64_t n = 0, nnz = 0;
     bool off32 = false;        // 4-byte offsets on the device
     bool owns = true;          // device arrays allocated by the library
+    bool symmetric = false;    // loaded with BFS_LOAD_SYMMETRIC (checked unless validation is skipped)
     void* d_off = nullptr;     // int64_t[n+1] or int32_t[n+1]
     int32_t* d_col = nullptr;  // int32_t[nnz]
     int64_t max_degree = 0;
@@ -205,8 +210,14 @@ void free_workspaces(bfs_graph* g);
 
 // Launchers (the kernels live in single.hip and multi.hip).
 void launch_single(bfs_graph* g, const bfs_tunables& t, Workspace* w, int32_t root, int32_t* levels,
-                   int32_t* parents, hipStream_t s);
+                   int32_t* parents, hipStream_t s, bool hybrid = false);
 void launch_single_stats(Workspace* w, hipStream_t s);
+// Stats of a run from its level array (hybrid runs scan no frontier rows in
+// bottom-up levels): reached and the sum of their degrees.
+void launch_single_stats_from_levels(bfs_graph* g, const bfs_tunables& t, Workspace* w, const int32_t* levels,
+                                     hipStream_t s);
+// Symmetry check of a resident CSR (a multiset hash of arcs against reversed arcs).
+bool csr_is_symmetric(const bfs_graph* g);
 void launch_fill_i32(int32_t* p, int64_t count, int32_t value, hipStream_t s);
 
 // Multi-source engine (multi.hip). A batch runs every level device-side with

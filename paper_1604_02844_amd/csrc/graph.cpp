@@ -455,7 +455,7 @@ bfs_graph* load_csr(int64_t n, int64_t nnz, const void* offsets, const int32_t* 
     if (nnz < 0) fail(BFS_E_INVALID_GRAPH, "nnz < 0");
     if (nnz > 4294967295LL) fail(BFS_E_INVALID_GRAPH, "nnz above 2^32 - 1 (arc offsets of the big-row lists are 32-bit)");
     if (!offsets || (!cols && nnz > 0)) fail(BFS_E_INVALID_ARG, "NULL CSR array");
-    if (flags & ~(BFS_LOAD_DEVICE_PTRS | BFS_LOAD_SKIP_VALIDATE | BFS_LOAD_OFFSETS_I32))
+    if (flags & ~(BFS_LOAD_DEVICE_PTRS | BFS_LOAD_SKIP_VALIDATE | BFS_LOAD_OFFSETS_I32 | BFS_LOAD_SYMMETRIC))
         fail(BFS_E_INVALID_ARG, "unknown load flag");
     const bool dev = flags & BFS_LOAD_DEVICE_PTRS;
     const bool o32 = flags & BFS_LOAD_OFFSETS_I32;
@@ -486,6 +486,11 @@ bfs_graph* load_csr(int64_t n, int64_t nnz, const void* offsets, const int32_t* 
             BFS_HIP(hipMemcpy(g->d_off, offsets, ob, hipMemcpyHostToDevice));
             if (nnz) BFS_HIP(hipMemcpy(g->d_col, cols, (size_t)nnz * 4, hipMemcpyHostToDevice));
             g->device_bytes += (int64_t)ob + nnz * 4;
+        }
+        if (flags & BFS_LOAD_SYMMETRIC) {
+            if (!(flags & BFS_LOAD_SKIP_VALIDATE) && !csr_is_symmetric(g))
+                fail(BFS_E_INVALID_GRAPH, "BFS_LOAD_SYMMETRIC: the arcs and the reversed arcs differ");
+            g->symmetric = true;
         }
         g->restore_grid = restore_grid_for(padded_words(n), g->cu_count);
         build_big_table(g->big, g->d_off, g->off32, n, default_tunables(nullptr).wave_max_degree, g->restore_grid,

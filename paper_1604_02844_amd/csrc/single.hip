@@ -89,6 +89,8 @@ struct SingleParams {
     uint32_t* hot_vis;
     int32_t hot_words;         // words of hot_vis (0 = off)
     int64_t hot_min_frontier;  // use the LDS copy only for frontiers of at least this many vertices
+    int64_t nnz;
+    int32_t hybrid;            // levels with large frontiers may run bottom-up (symmetric graphs)
 };
 
 
@@ -303,7 +305,10 @@ template <int BLOCK>
 struct ExpandShared {
     static constexpr int NW = BLOCK / 64;
     union {
-        uint32_t ring[NW][128];  // staged frontier vertices, one ring per wavefront
+        struct {
+            uint32_t ring[NW][128];    // staged frontier (or unvisited) vertices, one ring per wavefront
+            uint32_t bu_bits[NW][64];  // bottom-up: new visited bits of each wavefront's 64-word window
+        } w;
         struct {
             uint32_t segpre[kMaxRestoreGrid + 1];  // exclusive prefix of segment arcs
             uint32_t cntpre[kMaxRestoreGrid + 1];  // exclusive prefix of segment rows
@@ -438,6 +443,79 @@ __device__ __forceinline__ void expand_big(const SingleParams& p, ExpandShared<B
     }
 }
 
+// One bottom-up level (the direction-optimising hybrid): every vertex not yet
+// visited scans its neighbours and takes the first one in the frontier as its
+// parent, at level lvl. Each wavefront owns a contiguous run of visited words;
+// it compacts the unvisited vertices of 64 words at a time into its LDS ring,
+// gives one vertex to each lane, and collects the new bits of those 64 words
+// in LDS. The lane that owns a word then writes it once (vis = snapshot | new
+// bits), which marks it for the restoration pass. The frontier is read with
+// device-scope loads: another XCD wrote it in the previous launch.
+template <typename OffT, int BLOCK>
+__device__ __forceinline__ void bottom_up(const SingleParams& p, ExpandShared<BLOCK>& sh, int lvl) {
+    constexpr int NW = BLOCK / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int64_t waves = (int64_t)gridDim.x * NW;
+    const int64_t gw = (int64_t)blockIdx.x * NW + wid;
+    const int64_t wpw = (p.words + waves - 1) / waves;
+    const int64_t w0 = gw * wpw;
+    const int64_t w1 = w0 + wpw < p.words ? w0 + wpw : p.words;
+    uint32_t* ring = sh.x.w.ring[wid];
+    uint32_t* bits = sh.x.w.bu_bits[wid];
+    for (int64_t base = w0; base < w1; base += 64) {
+        const int64_t wi = base + lane;
+        uint32_t prev = ~0u;
+        if (wi < w1) prev = ld(p.vis_prev + wi);
+        uint32_t word = ~prev;
+        const int64_t first_v = wi * 32;
+        if (wi >= w1 || first_v >= p.n)
+            word = 0;
+        else if (first_v + 32 > p.n)
+            word &= (1u << (p.n - first_v)) - 1u;  // ids beyond n do not exist
+        bits[lane] = 0u;
+        uint32_t head = 0, tail = 0;
+        while (true) {
+            const bool has = word != 0;
+            const uint64_t m = __ballot(has);
+            const bool flush = m == 0;
+            if (has) {
+                const int b = __builtin_ctz(word);
+                word &= word - 1;
+                ring[(tail + rank_in(m)) & 127] = (uint32_t)(wi * 32 + b);
+            }
+            tail += __popcll(m);
+            while (tail - head >= 64 || (flush && tail != head)) {
+                const uint32_t cnt = tail - head < 64 ? tail - head : 64;
+                const bool valid = (uint32_t)lane < cnt;
+                const int32_t v = valid ? (int32_t)ring[(head + lane) & 127] : 0;
+                head += cnt;
+                int32_t par = -1;
+                if (valid) {
+                    const int64_t b = load_off<OffT>(p.off, v), e = load_off<OffT>(p.off, (int64_t)v + 1);
+                    for (int64_t j = b; j < e && par < 0; j += 4) {
+                        int32_t u[4];
+                        uint32_t f[4];
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) u[k] = j + k < e ? p.col[j + k] : -1;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k) f[k] = u[k] >= 0 ? ld(p.fr + (u[k] >> 5)) : 0u;
+#pragma unroll
+                        for (int k = 0; k < 4; ++k)
+                            if (par < 0 && u[k] >= 0 && ((f[k] >> (u[k] & 31)) & 1u)) par = u[k];
+                    }
+                }
+                if (par >= 0) {
+                    record(p, v, lvl + 1, out_id(p, par));
+                    atomicOr(bits + ((v >> 5) - base), 1u << (v & 31));
+                }
+            }
+            if (flush) break;
+        }
+        const uint32_t nb = bits[lane];
+        if (nb) st(p.vis + wi, prev | nb);
+    }
+}
+
 // a0: levels/parents = -1, bitmaps cleared, root seeded, counters reset.
 template <typename OffT, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_init(SingleParams p, int nslots) {
@@ -517,6 +595,10 @@ __global__ __launch_bounds__(BLOCK) void k_init(SingleParams p, int nslots) {
         p.ctrl->num_levels = 0;
         p.ctrl->reached = 0;
         p.ctrl->arcs = 0;
+        p.ctrl->dir[0] = 0;
+        p.ctrl->dir[1] = 0;
+        p.ctrl->visited[0] = 0;
+        p.ctrl->visited[1] = 0;
     }
 }
 
@@ -546,6 +628,37 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl) {
     }
     unsigned long long arcs = 0;
 
+    // Arcs of the frontier's rows above T2 (counted by the previous restore).
+    if (tid < 64) {
+        unsigned long long c = ld(&p.ctrl->bigarcs[lvl & 1][tid * kStripeStride]);
+        c = wave_sum(c);
+        if (tid == 0) sh.big_total = c;
+        if (bid == 0) st(&p.ctrl->bigarcs[(lvl + 1) & 1][tid * kStripeStride], 0ull);
+    }
+    __syncthreads();
+    const int64_t ta = (int64_t)sh.big_total;
+
+    // ---- direction (hybrid runs): every workgroup decides the same from the
+    // same counters. Bottom-up once the frontier's arcs exceed 1/14 of the arcs
+    // still unvisited; back to top-down when the frontier falls below n/24.
+    if (p.hybrid) {
+        const bool was_bu = ld(&p.ctrl->dir[lvl & 1]) != 0;
+        const unsigned long long seen = ld(&p.ctrl->visited[lvl & 1]);
+        const double nf = (double)sh.found;
+        const double mf = (double)ta + nf * ((double)p.nnz / (double)p.n);
+        const double unvisited = (double)p.n - (double)seen - nf;
+        const double mu = (double)p.nnz * (unvisited > 0.0 ? unvisited : 0.0) / (double)p.n;
+        const bool bu = was_bu ? nf * 24.0 >= (double)p.n : mf * 14.0 > mu;
+        if (bid == 0 && tid == 0) {
+            st(&p.ctrl->dir[(lvl + 1) & 1], bu ? 1 : 0);
+            st(&p.ctrl->visited[(lvl + 1) & 1], seen + sh.found);
+        }
+        if (bu) {
+            bottom_up<OffT, BLOCK>(p, sh, lvl);
+            return;
+        }
+    }
+
     // ---- LDS copy of the compact hot bitmap (exact at level start)
     extern __shared__ uint32_t hot_lds[];
     uint32_t hot_limit = 0;
@@ -558,14 +671,6 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl) {
     }
 
     // ---- rows of degree > T2: the level's big-row arcs, split evenly
-    if (tid < 64) {
-        unsigned long long c = ld(&p.ctrl->bigarcs[lvl & 1][tid * kStripeStride]);
-        c = wave_sum(c);
-        if (tid == 0) sh.big_total = c;
-        if (bid == 0) st(&p.ctrl->bigarcs[(lvl + 1) & 1][tid * kStripeStride], 0ull);
-    }
-    __syncthreads();
-    const int64_t ta = (int64_t)sh.big_total;
     if (ta > 0) {
         int64_t per = (ta + G - 1) / G;
         if (per < p.min_share) per = p.min_share;
@@ -591,11 +696,11 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl) {
             if (has) {
                 const int bit = __builtin_ctz(word);
                 word &= word - 1;
-                sh.x.ring[wid][(tail + rank_in(m)) & 127] = (uint32_t)(wi * 32 + bit);
+                sh.x.w.ring[wid][(tail + rank_in(m)) & 127] = (uint32_t)(wi * 32 + bit);
             }
             tail += __popcll(m);
             if (tail - head >= 64) {
-                const int32_t u = (int32_t)sh.x.ring[wid][(head + lane) & 127];
+                const int32_t u = (int32_t)sh.x.w.ring[wid][(head + lane) & 127];
                 head += 64;
                 process_batch<OffT, kAtomic>(p, u, true, lane, lvl + 1, arcs, hot_lds, hot_limit);
             }
@@ -604,7 +709,7 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl) {
     if (tail != head) {
         const int cnt = (int)(tail - head);
         const bool valid = lane < cnt;
-        const int32_t u = valid ? (int32_t)sh.x.ring[wid][(head + lane) & 127] : 0;
+        const int32_t u = valid ? (int32_t)sh.x.w.ring[wid][(head + lane) & 127] : 0;
         process_batch<OffT, kAtomic>(p, u, valid, lane, lvl + 1, arcs, hot_lds, hot_limit);
     }
 
@@ -755,6 +860,55 @@ __global__ void k_stats(Ctrl* c, const unsigned long long* arcs_slot, const unsi
     }
 }
 
+// Reached vertices and the sum of their degrees, from a level array.
+template <typename OffT>
+__global__ void k_stats_levels(const int32_t* lv, const OffT* off, int64_t n, Ctrl* c) {
+    unsigned long long r = 0, a = 0;
+    const int64_t gsize = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gsize)
+        if (lv[v] >= 0) {
+            ++r;
+            a += (unsigned long long)((int64_t)off[v + 1] - (int64_t)off[v]);
+        }
+    r = wave_sum(r);
+    a = wave_sum(a);
+    if ((threadIdx.x & 63) == 0) {
+        if (r) atomicAdd(&c->reached, r);
+        if (a) atomicAdd(&c->arcs, a);
+    }
+}
+
+// Symmetry check: the multiset of arcs and the multiset of reversed arcs have
+// the same sum of a 64-bit hash; one wavefront per row.
+__device__ __forceinline__ unsigned long long arc_hash(uint32_t a, uint32_t b) {
+    unsigned long long z = ((unsigned long long)a << 32 | b) + 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+template <typename OffT>
+__global__ void k_symmetry(const OffT* off, const int32_t* col, int64_t n, unsigned long long* sums) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    unsigned long long fwd = 0, rev = 0;
+    for (int64_t u = wave; u < n; u += waves) {
+        const int64_t b = (int64_t)off[u], e = (int64_t)off[u + 1];
+        for (int64_t j = b + lane; j < e; j += 64) {
+            const uint32_t v = (uint32_t)col[j];
+            fwd += arc_hash((uint32_t)u, v);
+            rev += arc_hash(v, (uint32_t)u);
+        }
+    }
+    fwd = wave_sum(fwd);
+    rev = wave_sum(rev);
+    if (lane == 0) {
+        atomicAdd(sums, fwd);
+        atomicAdd(sums + 1, rev);
+    }
+}
+
 // Columns of the degree-ordered copy: new row x is caller row new2old[x] with
 // every neighbour renamed; one wavefront per row, arcs in their original order.
 template <typename OffT>
@@ -801,14 +955,24 @@ struct Grids {
     int restore;
 };
 
+// Dynamic LDS available to one expansion workgroup next to its static LDS.
+template <int BLOCK>
+int lds_dynamic_cap() {
+    constexpr int kLdsPerCu = 160 * 1024;
+    const int left = kLdsPerCu - (int)sizeof(ExpandShared<BLOCK>) - 1024;  // margin for compiler temporaries
+    return std::min(left, kMaxHotWords * 4);
+}
+
 
 template <typename OffT, int BLOCK, bool kAtomic>
 Grids grids_for(bfs_graph* g, const bfs_tunables& t, int64_t nslots, int hot_words) {
-    // Dynamic LDS (the hot snapshot) beyond the default limit must be allowed once.
+    // Dynamic LDS (the hot snapshot) beyond the default limit must be allowed
+    // once: up to what fits beside the static LDS in the 160 KiB of a CU.
+    const int cap = lds_dynamic_cap<BLOCK>();
     static const bool lds_ok = hipFuncSetAttribute(reinterpret_cast<const void*>(k_expand<OffT, BLOCK, kAtomic>),
-                                                   hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                   kMaxHotWords * 4) == hipSuccess;
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize, cap) == hipSuccess;
     if (!lds_ok) fail(BFS_E_DEVICE, "cannot enable dynamic LDS for the expansion kernel");
+    if (hot_words * 4 > cap) fail(BFS_E_INVALID_ARG, "hot bitmap does not fit in LDS beside this workgroup size");
     const int occ = occupancy_of(k_expand<OffT, BLOCK, kAtomic>, BLOCK, (size_t)hot_words * 4);
     // On gfx950 one workgroup per CU fewer than the occupancy query reports is
     // resident at once (measured: with the reported count, one workgroup per CU
@@ -849,7 +1013,7 @@ void launch_typed(bfs_graph* g, const bfs_tunables& t, Workspace* w, SingleParam
 }  // namespace
 
 void launch_single(bfs_graph* g, const bfs_tunables& t, Workspace* w, int32_t root, int32_t* levels,
-                   int32_t* parents, hipStream_t s) {
+                   int32_t* parents, hipStream_t s, bool hybrid) {
     // Host-side checks of what the kernels assume about their buffers.
     if (root < 0 || root >= g->n) fail(BFS_E_ROOT_RANGE, "root out of range");
     if (w->words * 32 < g->n || w->words % 64 != 0) fail(BFS_E_INTERNAL, "workspace bitmaps too small");
@@ -893,6 +1057,9 @@ void launch_single(bfs_graph* g, const bfs_tunables& t, Workspace* w, int32_t ro
     if ((int64_t)p.hot_words * 32 > w->words || p.hot_words % 2 != 0 || p.hot_words > w->hot_capacity)
         fail(BFS_E_INTERNAL, "hot bitmap larger than its buffer");
     if (w->big_capacity < bt.num_big) fail(BFS_E_INTERNAL, "big-row list too small");
+    if (hybrid && !g->symmetric) fail(BFS_E_INVALID_ARG, "bottom-up levels need a graph loaded as symmetric");
+    p.nnz = g->nnz;
+    p.hybrid = hybrid ? 1 : 0;
     const bool off32 = !h && g->off32;
     const bool atomic = t.update_mode == 2;
 #define BFS_LAUNCH(OFFT, BS)                                         \
@@ -945,6 +1112,43 @@ void validate_device_csr(const void* off, bool off32, const int32_t* col, int64_
     }
     (void)hipFree(d_err);
     if (err) fail(BFS_E_INVALID_GRAPH, "device CSR failed validation (code " + std::to_string(err) + ")");
+}
+
+void launch_single_stats_from_levels(bfs_graph* g, const bfs_tunables& t, Workspace* w, const int32_t* levels,
+                                     hipStream_t s) {
+    const bool copy = hot_count(g, t) > 0;
+    const int32_t* lv = copy ? w->lv_new : levels;
+    if (!lv) fail(BFS_E_INTERNAL, "no level array for the stats");
+    BFS_HIP(hipMemsetAsync(&w->ctrl->reached, 0, 2 * sizeof(unsigned long long), s));
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((g->n + 255) / 256, (int64_t)g->cu_count * 8));
+    if (copy)
+        k_stats_levels<int64_t><<<blocks, 256, 0, s>>>(lv, g->hot->d_off, g->n, w->ctrl);
+    else if (g->off32)
+        k_stats_levels<int32_t><<<blocks, 256, 0, s>>>(lv, static_cast<const int32_t*>(g->d_off), g->n, w->ctrl);
+    else
+        k_stats_levels<int64_t><<<blocks, 256, 0, s>>>(lv, static_cast<const int64_t*>(g->d_off), g->n, w->ctrl);
+    BFS_HIP(hipGetLastError());
+}
+
+bool csr_is_symmetric(const bfs_graph* g) {
+    unsigned long long* d = nullptr;
+    unsigned long long h[2] = {0, 0};
+    BFS_HIP(hipMalloc(&d, 2 * sizeof(unsigned long long)));
+    try {
+        BFS_HIP(hipMemset(d, 0, 2 * sizeof(unsigned long long)));
+        const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((g->n + 3) / 4, (int64_t)g->cu_count * 32));
+        if (g->off32)
+            k_symmetry<int32_t><<<blocks, 256>>>(static_cast<const int32_t*>(g->d_off), g->d_col, g->n, d);
+        else
+            k_symmetry<int64_t><<<blocks, 256>>>(static_cast<const int64_t*>(g->d_off), g->d_col, g->n, d);
+        BFS_HIP(hipGetLastError());
+        BFS_HIP(hipMemcpy(h, d, sizeof(h), hipMemcpyDeviceToHost));
+    } catch (...) {
+        (void)hipFree(d);
+        throw;
+    }
+    (void)hipFree(d);
+    return h[0] == h[1];
 }
 
 void launch_relabel_cols(const bfs_graph* g, const int64_t* d_noff, const int32_t* d_new2old,

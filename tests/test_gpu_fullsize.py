@@ -34,6 +34,21 @@ def test_single_root_full_scale(scale, oracle_roots, cert_roots):
         assert st["reached"] == int((lv >= 0).sum())
 
 
+def test_hybrid_rmat24():
+    """Direction-optimising runs at full size, in the configuration the hybrid
+    bench times (degree-ordered copy on by default at this size)."""
+    torch_mod()
+    g = graphgen.cached("rmat", scale=24, edgefactor=16, seed=1)
+    dg = load(g, symmetric=True)
+    roots = graphgen.pick_roots(g, 64, seed=2)
+    check_root(g, dg, int(roots[0]), flags=bfs.BFS_HYBRID)
+    for r in roots[1:4]:
+        print(f"[case] certify hybrid scale 24 root {r}", flush=True)
+        lv, pa, st = gpu_run(dg, int(r), flags=bfs.BFS_HYBRID)
+        certify_row(g, r, lv, pa)
+        assert st["reached"] == int((lv >= 0).sum())
+
+
 def test_batch_rmat22_64_roots():
     torch = torch_mod()
     g = graphgen.cached("rmat", scale=22, edgefactor=16, seed=1)

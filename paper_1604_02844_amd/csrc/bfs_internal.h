@@ -66,6 +66,7 @@ struct Workspace {
     uint32_t* seg_arcs = nullptr;
     int32_t big_capacity = 0;
     uint32_t* hot_vis = nullptr;    // compact visited bitmap of the hot vertices (ids 32r)
+    uint32_t* hot_fr = nullptr;     // compact frontier bitmap of the hot vertices
     int32_t hot_capacity = 0;       // its words
     int32_t* lv_new = nullptr;      // levels in the degree-ordered ids (runs on the copy)
     Ctrl* host_ctrl = nullptr;      // pinned mirror for stats
@@ -126,6 +127,7 @@ struct BigTable {
     int64_t* d_big_prefix = nullptr;
     uint32_t* d_bigmap = nullptr;
     int32_t* d_seg_start = nullptr;
+    uint32_t* d_nzmap = nullptr;  // vertices with at least one arc (the only ones a bottom-up level can find)
     int64_t bytes = 0;
 };
 
@@ -191,7 +193,7 @@ void build_hot_layout(bfs_graph* g, int32_t hot, int32_t threshold);
 void free_hot_layout(bfs_graph* g);
 // Device part of the copy (single.hip): new columns of every new row.
 void launch_relabel_cols(const bfs_graph* g, const int64_t* d_noff, const int32_t* d_new2old,
-                         const int32_t* d_old2new, int32_t* d_ncol);
+                         const int32_t* d_old2new, int32_t* d_ncol, int32_t hot);
 int64_t padded_words(int64_t n);
 // Blocks of the restore pass: 256-word chunks, chunk c handled by block c % grid.
 constexpr int kRestoreBlock = 256;

@@ -80,6 +80,7 @@ void free_big_table(BigTable& t) {
     if (t.d_big_prefix) (void)hipFree(t.d_big_prefix);
     if (t.d_bigmap) (void)hipFree(t.d_bigmap);
     if (t.d_seg_start) (void)hipFree(t.d_seg_start);
+    if (t.d_nzmap) (void)hipFree(t.d_nzmap);
     t = BigTable{};
 }
 
@@ -93,13 +94,14 @@ void build_big_table(BigTable& t, const void* d_off, bool off32, int64_t n, int3
     t.threshold = threshold;
     const std::vector<int64_t> off = host_offsets(d_off, off32, n);
     const int64_t words = padded_words(n);
-    std::vector<uint32_t> bigmap((size_t)words, 0u);
+    std::vector<uint32_t> bigmap((size_t)words, 0u), nzmap((size_t)words, 0u);
     std::vector<int32_t> big;
     std::vector<int64_t> prefix(1, 0);
     int64_t maxd = 0;
     for (int64_t v = 0; v < n; ++v) {
         const int64_t d = off[(size_t)v + 1] - off[(size_t)v];
         maxd = std::max(maxd, d);
+        if (d > 0) nzmap[(size_t)(v >> 5)] |= 1u << (v & 31);
         if (d > threshold) {
             big.push_back((int32_t)v);
             prefix.push_back(prefix.back() + d);
@@ -116,6 +118,8 @@ void build_big_table(BigTable& t, const void* d_off, bool off32, int64_t n, int3
         if (!big.empty()) BFS_HIP(hipMemcpy(t.d_big, big.data(), big.size() * 4, hipMemcpyHostToDevice));
         BFS_HIP(hipMemcpy(t.d_big_prefix, prefix.data(), prefix.size() * 8, hipMemcpyHostToDevice));
         BFS_HIP(hipMemcpy(t.d_bigmap, bigmap.data(), (size_t)words * 4, hipMemcpyHostToDevice));
+        BFS_HIP(hipMalloc(&t.d_nzmap, (size_t)words * 4));
+        BFS_HIP(hipMemcpy(t.d_nzmap, nzmap.data(), (size_t)words * 4, hipMemcpyHostToDevice));
         // Segment capacities of the restore pass: the big rows inside the
         // chunks that each restore block visits.
         std::vector<int32_t> seg((size_t)restore_grid + 1, 0);
@@ -126,7 +130,7 @@ void build_big_table(BigTable& t, const void* d_off, bool off32, int64_t n, int3
         for (int b = 0; b < restore_grid; ++b) seg[(size_t)b + 1] += seg[(size_t)b];
         BFS_HIP(hipMalloc(&t.d_seg_start, seg.size() * 4));
         BFS_HIP(hipMemcpy(t.d_seg_start, seg.data(), seg.size() * 4, hipMemcpyHostToDevice));
-        t.bytes = (int64_t)std::max<size_t>(big.size(), 1) * 4 + (int64_t)prefix.size() * 8 + words * 4 +
+        t.bytes = (int64_t)std::max<size_t>(big.size(), 1) * 4 + (int64_t)prefix.size() * 8 + words * 8 +
                   (int64_t)seg.size() * 4;
     } catch (...) {
         free_big_table(t);
@@ -154,9 +158,10 @@ void free_hot_layout(bfs_graph* g) {
 }
 
 // The degree-ordered copy. Hot vertices: the `hot` highest degrees (ties to
-// the lower id), placed at ids 32r in increasing caller-id order; all other
-// vertices fill the remaining ids in increasing caller-id order. Rows keep
-// their arc order; columns are renamed on the device.
+// the lower id), placed at ids 32r by decreasing degree; all other vertices
+// fill the remaining ids in increasing caller-id order. Columns are renamed on
+// the device and every row lists its hot neighbours first (each part in the
+// original arc order), so a bottom-up scan meets the likely parents first.
 void build_hot_layout(bfs_graph* g, int32_t hot, int32_t threshold) {
     free_hot_layout(g);
     if (hot <= 0) return;
@@ -182,6 +187,10 @@ void build_hot_layout(bfs_graph* g, int32_t hot, int32_t threshold) {
         }
     }
     if ((int64_t)hot_ids.size() != hot) fail(BFS_E_INTERNAL, "hot vertex selection");
+    // Hot rank r goes to the r-th highest degree (ties to the lower id).
+    std::stable_sort(hot_ids.begin(), hot_ids.end(), [&](int32_t a, int32_t b) {
+        return off[(size_t)a + 1] - off[(size_t)a] > off[(size_t)b + 1] - off[(size_t)b];
+    });
     std::vector<int32_t> new2old((size_t)n), old2new((size_t)n);
     int64_t cold = 0;
     for (int64_t x = 0; x < n; ++x) {
@@ -209,7 +218,7 @@ void build_hot_layout(bfs_graph* g, int32_t hot, int32_t threshold) {
         BFS_HIP(hipMemcpy(h->d_off, noff.data(), noff.size() * 8, hipMemcpyHostToDevice));
         BFS_HIP(hipMemcpy(h->d_new2old, new2old.data(), (size_t)n * 4, hipMemcpyHostToDevice));
         BFS_HIP(hipMemcpy(d_old2new, old2new.data(), (size_t)n * 4, hipMemcpyHostToDevice));
-        launch_relabel_cols(g, h->d_off, h->d_new2old, d_old2new, h->d_col);
+        launch_relabel_cols(g, h->d_off, h->d_new2old, d_old2new, h->d_col, hot);
         BFS_HIP(hipDeviceSynchronize());
         BFS_HIP(hipFree(d_old2new));
         d_old2new = nullptr;
@@ -329,7 +338,7 @@ Workspace* acquire_ws(bfs_graph* g, hipStream_t s) {
         const size_t bmb = (size_t)w->words * 4;
         const size_t listb = (size_t)w->big_capacity * 8 + (size_t)(g->restore_grid + 1) * 8;
         w->hot_capacity = (int)std::min<int64_t>(w->words / 32, kMaxHotWords);
-        const size_t hotb = (size_t)w->hot_capacity * 4;
+        const size_t hotb = (size_t)w->hot_capacity * 8;  // visited and frontier bits
         const size_t lvb = g->hot ? (size_t)g->n * 4 : 0;  // levels in the degree-ordered ids
         const size_t total = bmb * 3 + sizeof(Ctrl) + (size_t)w->nslots * 2 * 8 + listb + hotb + lvb;
         char* base = nullptr;
@@ -345,6 +354,7 @@ Workspace* acquire_ws(bfs_graph* g, hipStream_t s) {
         w->seg_cnt = reinterpret_cast<uint32_t*>(lp + (size_t)w->big_capacity * 8);
         w->seg_arcs = w->seg_cnt + (g->restore_grid + 1);
         w->hot_vis = reinterpret_cast<uint32_t*>(lp + listb);
+        w->hot_fr = w->hot_vis + w->hot_capacity;
         w->lv_new = lvb ? reinterpret_cast<int32_t*>(lp + listb + hotb) : nullptr;
         BFS_HIP(hipMemset(w->ctrl, 0, sizeof(Ctrl)));
         BFS_HIP(hipHostMalloc(&w->host_ctrl, sizeof(Ctrl), hipHostMallocDefault));

@@ -56,6 +56,7 @@ namespace {
 constexpr int kUnroll = 2;     // arcs per lane in flight: one wavefront per row (T1 < d <= T2)
 constexpr int kLbsUnroll = 4;  // arcs per lane in flight: packed rows (d <= T1)
 constexpr int kBigUnroll = 4;  // arcs per lane in flight: rows above T2
+constexpr int kBuFirst = 4;    // bottom-up: arcs each lane checks before its wavefront helps
 
 struct SingleParams {
     const void* off;
@@ -75,6 +76,7 @@ struct SingleParams {
     unsigned long long* arcs_slot;     // per expansion block
     unsigned long long* reached_slot;  // per restore block
     const uint32_t* bigmap;   // rows with degree > T2
+    const uint32_t* nzmap;    // rows with degree > 0
     int32_t* bl_u;            // big frontier rows, one segment per restore block
     uint32_t* bl_pre;         // their exclusive arc offsets within the segment
     uint32_t* seg_cnt;        // rows per segment
@@ -87,7 +89,8 @@ struct SingleParams {
     // hot_vis is their compact visited bitmap (bit r), which the restore pass
     // keeps exact and expansion workgroups copy into LDS.
     uint32_t* hot_vis;
-    int32_t hot_words;         // words of hot_vis (0 = off)
+    uint32_t* hot_fr;          // compact bitmap of the hot vertices in the frontier (exact per level)
+    int32_t hot_words;         // words of hot_vis / hot_fr (0 = off)
     int64_t hot_min_frontier;  // use the LDS copy only for frontiers of at least this many vertices
     int64_t nnz;
     int32_t hybrid;            // levels with large frontiers may run bottom-up (symmetric graphs)
@@ -452,7 +455,16 @@ __device__ __forceinline__ void expand_big(const SingleParams& p, ExpandShared<B
 // bits), which marks it for the restoration pass. The frontier is read with
 // device-scope loads: another XCD wrote it in the previous launch.
 template <typename OffT, int BLOCK>
-__device__ __forceinline__ void bottom_up(const SingleParams& p, ExpandShared<BLOCK>& sh, int lvl) {
+__device__ __forceinline__ void bottom_up(const SingleParams& p, ExpandShared<BLOCK>& sh, int lvl,
+                                          const uint32_t* hot, uint32_t hot_limit, bool cold_empty) {
+    // Is u in the frontier? Hot ids from the LDS copy of the frontier's hot
+    // bits; others from the frontier bitmap, unless the frontier has none.
+    auto in_frontier = [&](int32_t u) -> bool {
+        const uint32_t r = (uint32_t)u >> 5;
+        if ((u & 31) == 0 && r < hot_limit) return (hot[r >> 5] >> (r & 31)) & 1u;
+        if (cold_empty) return false;
+        return (ld(p.fr + r) >> (u & 31)) & 1u;
+    };
     constexpr int NW = BLOCK / 64;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int64_t waves = (int64_t)gridDim.x * NW;
@@ -464,9 +476,12 @@ __device__ __forceinline__ void bottom_up(const SingleParams& p, ExpandShared<BL
     uint32_t* bits = sh.x.w.bu_bits[wid];
     for (int64_t base = w0; base < w1; base += 64) {
         const int64_t wi = base + lane;
-        uint32_t prev = ~0u;
-        if (wi < w1) prev = ld(p.vis_prev + wi);
-        uint32_t word = ~prev;
+        uint32_t prev = ~0u, nz = 0u;
+        if (wi < w1) {
+            prev = ld(p.vis_prev + wi);
+            nz = p.nzmap[wi];
+        }
+        uint32_t word = ~prev & nz;  // vertices without arcs cannot be reached: skip them
         const int64_t first_v = wi * 32;
         if (wi >= w1 || first_v >= p.n)
             word = 0;
@@ -489,20 +504,39 @@ __device__ __forceinline__ void bottom_up(const SingleParams& p, ExpandShared<BL
                 const bool valid = (uint32_t)lane < cnt;
                 const int32_t v = valid ? (int32_t)ring[(head + lane) & 127] : 0;
                 head += cnt;
+                // Phase 1: each lane checks the first kBuFirst arcs of its vertex
+                // (independent loads); most vertices settle here.
                 int32_t par = -1;
+                int64_t b = 0, e = 0;
                 if (valid) {
-                    const int64_t b = load_off<OffT>(p.off, v), e = load_off<OffT>(p.off, (int64_t)v + 1);
-                    for (int64_t j = b; j < e && par < 0; j += 4) {
-                        int32_t u[4];
-                        uint32_t f[4];
+                    b = load_off<OffT>(p.off, v);
+                    e = load_off<OffT>(p.off, (int64_t)v + 1);
+                    int32_t u[kBuFirst];
+                    bool f[kBuFirst];
 #pragma unroll
-                        for (int k = 0; k < 4; ++k) u[k] = j + k < e ? p.col[j + k] : -1;
+                    for (int k = 0; k < kBuFirst; ++k) u[k] = b + k < e ? p.col[b + k] : -1;
 #pragma unroll
-                        for (int k = 0; k < 4; ++k) f[k] = u[k] >= 0 ? ld(p.fr + (u[k] >> 5)) : 0u;
+                    for (int k = 0; k < kBuFirst; ++k) f[k] = u[k] >= 0 && in_frontier(u[k]);
 #pragma unroll
-                        for (int k = 0; k < 4; ++k)
-                            if (par < 0 && u[k] >= 0 && ((f[k] >> (u[k] & 31)) & 1u)) par = u[k];
+                    for (int k = 0; k < kBuFirst; ++k)
+                        if (par < 0 && f[k]) par = u[k];
+                }
+                // Phase 2: longer rows without a hit are scanned by the whole
+                // wavefront, 64 arcs at a time, until the first frontier neighbour.
+                uint64_t longm = __ballot(valid && par < 0 && e - b > kBuFirst);
+                while (longm) {
+                    const int src = __builtin_ctzll(longm);
+                    longm &= longm - 1;
+                    const int64_t lb = shfl64(b, src) + kBuFirst, le = shfl64(e, src);
+                    int32_t found = -1;
+                    for (int64_t j0 = lb; j0 < le && found < 0; j0 += 64) {
+                        const int64_t j = j0 + lane;
+                        const int32_t u = j < le ? p.col[j] : -1;
+                        const bool hit = u >= 0 && in_frontier(u);
+                        const uint64_t hm = __ballot(hit);
+                        if (hm) found = __shfl(u, __builtin_ctzll(hm), 64);
                     }
+                    if (lane == src) par = found;
                 }
                 if (par >= 0) {
                     record(p, v, lvl + 1, out_id(p, par));
@@ -570,8 +604,11 @@ __global__ __launch_bounds__(BLOCK) void k_init(SingleParams p, int nslots) {
         p.reached_slot[i] = 0;
     }
     const bool root_hot = (p.root & 31) == 0 && rw < (int64_t)p.hot_words * 32;
-    for (int64_t i = gtid; i < p.hot_words; i += gsize)
-        p.hot_vis[i] = (root_hot && i == (rw >> 5)) ? 1u << (rw & 31) : 0u;
+    for (int64_t i = gtid; i < p.hot_words; i += gsize) {
+        const uint32_t x = (root_hot && i == (rw >> 5)) ? 1u << (rw & 31) : 0u;
+        p.hot_vis[i] = x;
+        p.hot_fr[i] = x;
+    }
     // The root is the whole first frontier; when its row is big it is the only
     // entry of the big-row list (in the segment of its restore block).
     const bool root_big = (p.bigmap[rw] >> (p.root & 31)) & 1u;
@@ -654,7 +691,30 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl) {
             st(&p.ctrl->visited[(lvl + 1) & 1], seen + sh.found);
         }
         if (bu) {
-            bottom_up<OffT, BLOCK>(p, sh, lvl);
+            // LDS copy of the frontier's hot bits, and whether the frontier has
+            // any vertex outside the hot set.
+            extern __shared__ uint32_t hot_lds[];
+            uint32_t hlim = 0;
+            bool cold_empty = false;
+            if (p.hot_words > 0) {
+                const unsigned long long* src = reinterpret_cast<const unsigned long long*>(p.hot_fr);
+                unsigned long long* dst = reinterpret_cast<unsigned long long*>(hot_lds);
+                unsigned long long cnt = 0;
+                for (int i = tid; i < p.hot_words / 2; i += BLOCK) {
+                    const unsigned long long x = ld(src + i);
+                    dst[i] = x;
+                    cnt += (unsigned long long)__popcll(x);
+                }
+                cnt = wave_sum(cnt);
+                if (lane == 0) sh.red[wid] = cnt;
+                __syncthreads();
+                unsigned long long hot_in = 0;
+                for (int i = 0; i < NW; ++i) hot_in += sh.red[i];
+                cold_empty = hot_in == sh.found;
+                hlim = (uint32_t)p.hot_words * 32u;
+                __syncthreads();
+            }
+            bottom_up<OffT, BLOCK>(p, sh, lvl, hot_lds, hlim, cold_empty);
             return;
         }
     }
@@ -791,6 +851,7 @@ __global__ __launch_bounds__(kRestoreBlock) void k_restore(SingleParams p, int l
                 uint32_t* hw = p.hot_vis + (w >> 5);
                 st(hw, ld(hw) | bits);
             }
+            if ((lane & 31) == 0 && w < (int64_t)p.hot_words * 32) st(p.hot_fr + (w >> 5), bits);
         }
         if (w < p.words) {
             st(p.fr + w, exact);
@@ -913,14 +974,52 @@ __global__ void k_symmetry(const OffT* off, const int32_t* col, int64_t n, unsig
 // every neighbour renamed; one wavefront per row, arcs in their original order.
 template <typename OffT>
 __global__ void k_relabel_cols(const OffT* off, const int32_t* col, const int64_t* noff, const int32_t* new2old,
-                               const int32_t* old2new, int32_t* ncol, int64_t n) {
+                               const int32_t* old2new, int32_t* ncol, int64_t n, int32_t hot) {
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t x = wave; x < n; x += waves) {
         const int64_t u = new2old[x];
         const int64_t b = (int64_t)off[u], d = (int64_t)off[u + 1] - b, nb = noff[x];
-        for (int64_t j = lane; j < d; j += 64) ncol[nb + j] = old2new[col[b + j]];
+        if (d <= 64) {
+            // Short row: one sort across the wavefront. Hot neighbours first by
+            // rank (highest degree first), then the others in arc order.
+            const int32_t v = lane < d ? old2new[col[b + lane]] : -1;
+            const bool is_hot = v >= 0 && (v & 31) == 0 && (v >> 5) < hot;
+            unsigned long long key = v < 0 ? ~0ull
+                                           : (is_hot ? (unsigned long long)(uint32_t)v
+                                                     : (1ull << 40) | (unsigned long long)lane);
+            int32_t val = v;
+            for (int k = 2; k <= 64; k <<= 1) {
+                for (int j = k >> 1; j > 0; j >>= 1) {
+                    const unsigned long long ok_ = ((unsigned long long)__shfl_xor((int)(key >> 32), j, 64) << 32) |
+                                                   (uint32_t)__shfl_xor((int)(uint32_t)key, j, 64);
+                    const int32_t ov = __shfl_xor(val, j, 64);
+                    const bool up = (lane & k) == 0;          // this pair sorts ascending
+                    const bool low = (lane & j) == 0;         // this lane keeps the smaller key
+                    const bool take = (low == up) ? ok_ < key : ok_ > key;
+                    if (take) {
+                        key = ok_;
+                        val = ov;
+                    }
+                }
+            }
+            if (lane < d) ncol[nb + lane] = val;
+            continue;
+        }
+        // Long row: two stable passes, hot neighbours (ids 32r, r < hot) first, then the rest.
+        int64_t at = 0;
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int64_t j0 = 0; j0 < d; j0 += 64) {
+                const int64_t j = j0 + lane;
+                const int32_t v = j < d ? old2new[col[b + j]] : -1;
+                const bool is_hot = v >= 0 && (v & 31) == 0 && (v >> 5) < hot;
+                const bool take = v >= 0 && (pass == 0 ? is_hot : !is_hot);
+                const uint64_t m = __ballot(take);
+                if (take) ncol[nb + at + rank_in(m)] = v;
+                at += __popcll(m);
+            }
+        }
     }
 }
 
@@ -1043,6 +1142,7 @@ void launch_single(bfs_graph* g, const bfs_tunables& t, Workspace* w, int32_t ro
     p.arcs_slot = w->slots;
     p.reached_slot = w->slots + w->nslots;
     p.bigmap = bt.d_bigmap;
+    p.nzmap = bt.d_nzmap;
     p.bl_u = w->bl_u;
     p.bl_pre = w->bl_pre;
     p.seg_cnt = w->seg_cnt;
@@ -1053,6 +1153,7 @@ void launch_single(bfs_graph* g, const bfs_tunables& t, Workspace* w, int32_t ro
     p.min_share = t.chunk_arcs > 0 ? t.chunk_arcs : 1024;
     p.hot_words = h ? h->hot / 32 : 0;
     p.hot_vis = w->hot_vis;
+    p.hot_fr = w->hot_fr;
     p.hot_min_frontier = std::max<int64_t>(4096, g->n / 256);
     if ((int64_t)p.hot_words * 32 > w->words || p.hot_words % 2 != 0 || p.hot_words > w->hot_capacity)
         fail(BFS_E_INTERNAL, "hot bitmap larger than its buffer");
@@ -1152,14 +1253,14 @@ bool csr_is_symmetric(const bfs_graph* g) {
 }
 
 void launch_relabel_cols(const bfs_graph* g, const int64_t* d_noff, const int32_t* d_new2old,
-                         const int32_t* d_old2new, int32_t* d_ncol) {
+                         const int32_t* d_old2new, int32_t* d_ncol, int32_t hot) {
     const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((g->n + 3) / 4, (int64_t)g->cu_count * 32));
     if (g->off32)
         k_relabel_cols<int32_t><<<blocks, 256>>>(static_cast<const int32_t*>(g->d_off), g->d_col, d_noff, d_new2old,
-                                                 d_old2new, d_ncol, g->n);
+                                                 d_old2new, d_ncol, g->n, hot);
     else
         k_relabel_cols<int64_t><<<blocks, 256>>>(static_cast<const int64_t*>(g->d_off), g->d_col, d_noff, d_new2old,
-                                                 d_old2new, d_ncol, g->n);
+                                                 d_old2new, d_ncol, g->n, hot);
     BFS_HIP(hipGetLastError());
 }
 

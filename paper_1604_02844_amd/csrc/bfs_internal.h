@@ -68,7 +68,7 @@ struct Workspace {
     uint32_t* hot_vis = nullptr;    // compact visited bitmap of the hot vertices (ids 32r)
     uint32_t* hot_fr = nullptr;     // compact frontier bitmap of the hot vertices
     int32_t hot_capacity = 0;       // its words
-    int32_t* lv_new = nullptr;      // levels in the degree-ordered ids (runs on the copy)
+    int32_t* run_rec = nullptr;     // {level, parent} per degree-ordered id (runs on the copy)
     Ctrl* host_ctrl = nullptr;      // pinned mirror for stats
     int32_t* out_levels = nullptr;  // staging for BFS_OUT_HOST
     int32_t* out_parents = nullptr;

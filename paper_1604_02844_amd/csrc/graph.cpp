@@ -339,8 +339,10 @@ Workspace* acquire_ws(bfs_graph* g, hipStream_t s) {
         const size_t listb = (size_t)w->big_capacity * 8 + (size_t)(g->restore_grid + 1) * 8;
         w->hot_capacity = (int)std::min<int64_t>(w->words / 32, kMaxHotWords);
         const size_t hotb = (size_t)w->hot_capacity * 8;  // visited and frontier bits
-        const size_t lvb = g->hot ? (size_t)g->n * 4 : 0;  // levels in the degree-ordered ids
-        const size_t total = bmb * 3 + sizeof(Ctrl) + (size_t)w->nslots * 2 * 8 + listb + hotb + lvb;
+        const size_t recb = g->hot ? (size_t)g->n * 8 : 0;  // {level, parent} in the degree-ordered ids
+        const size_t pre_rec = bmb * 3 + sizeof(Ctrl) + (size_t)w->nslots * 2 * 8 + listb + hotb;
+        const size_t rec_at = (pre_rec + 255) & ~(size_t)255;
+        const size_t total = rec_at + recb;
         char* base = nullptr;
         BFS_HIP(hipMalloc(&base, total));
         w->vis = reinterpret_cast<uint32_t*>(base);
@@ -355,7 +357,7 @@ Workspace* acquire_ws(bfs_graph* g, hipStream_t s) {
         w->seg_arcs = w->seg_cnt + (g->restore_grid + 1);
         w->hot_vis = reinterpret_cast<uint32_t*>(lp + listb);
         w->hot_fr = w->hot_vis + w->hot_capacity;
-        w->lv_new = lvb ? reinterpret_cast<int32_t*>(lp + listb + hotb) : nullptr;
+        w->run_rec = recb ? reinterpret_cast<int32_t*>(base + rec_at) : nullptr;
         BFS_HIP(hipMemset(w->ctrl, 0, sizeof(Ctrl)));
         BFS_HIP(hipHostMalloc(&w->host_ctrl, sizeof(Ctrl), hipHostMallocDefault));
         BFS_HIP(hipEventCreate(&w->ev_start));

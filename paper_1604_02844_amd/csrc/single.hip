@@ -64,7 +64,10 @@ struct SingleParams {
     int32_t n;
     int32_t root;
     int64_t words;  // padded 32-bit words per bitmap (multiple of 64)
-    int32_t* lv;               // levels by the run's vertex ids (read by restore and claims)
+    // Levels by the run's vertex ids (read by restore and claims): the caller's
+    // level array, or on the degree-ordered copy the level half of an
+    // interleaved {level, parent} record per run id.
+    int32_t* lv;
     int32_t* out_lv;           // the caller's levels and parents, by caller ids
     int32_t* out_pa;
     const int32_t* new2old;    // run id -> caller id on the degree-ordered copy, else nullptr
@@ -171,12 +174,20 @@ __device__ __forceinline__ unsigned long long* stripe(Ctrl* c, int parity, int s
 // Caller id of run id u.
 __device__ __forceinline__ int32_t out_id(const SingleParams& p, int32_t u) { return p.new2old ? p.new2old[u] : u; }
 
-// Discovery of run id v at level lvl from the caller-id parent par.
+// Index of run id v's level in p.lv.
+__device__ __forceinline__ int64_t lv_at(const SingleParams& p, int64_t v) { return p.new2old ? 2 * v : v; }
+
+// Discovery of run id v at level lvl from the caller-id parent par. On the
+// degree-ordered copy this is one 8-byte record at the run id; the caller's
+// arrays are filled by one pass in run order after the last level (cold ids
+// keep the caller's order, so that pass writes nearly coalesced).
 __device__ __forceinline__ void record(const SingleParams& p, int32_t v, int lvl, int32_t par) {
-    p.lv[v] = lvl;
-    const int32_t o = out_id(p, v);
-    if (p.new2old) p.out_lv[o] = lvl;
-    p.out_pa[o] = par;
+    if (p.new2old) {
+        *reinterpret_cast<int2*>(p.lv + 2 * (int64_t)v) = make_int2(lvl, par);
+    } else {
+        p.lv[v] = lvl;
+        p.out_pa[v] = par;
+    }
 }
 
 // Hot ids (32r with r < hot_limit) are first looked up in the workgroup's LDS
@@ -220,7 +231,7 @@ __device__ __forceinline__ void visit_arcs(const SingleParams& p, const int64_t 
         // reached in any earlier level.
         int lv_now[U];
 #pragma unroll
-        for (int i = 0; i < U; ++i) lv_now[i] = (!(w[i] & (1u << (v[i] & 31)))) ? ld(p.lv + v[i]) : 0;
+        for (int i = 0; i < U; ++i) lv_now[i] = (!(w[i] & (1u << (v[i] & 31)))) ? ld(p.lv + lv_at(p, v[i])) : 0;
 #pragma unroll
         for (int i = 0; i < U; ++i) {
             const uint32_t b = 1u << (v[i] & 31);
@@ -252,11 +263,20 @@ __device__ __forceinline__ void expand_row(const SingleParams& p, int64_t beg, i
 }
 
 // One batch of up to 64 staged frontier vertices (valid lanes only). Rows of
-// degree <= T1 are expanded packed: arc a of the batch belongs to the entry e
-// with excl[e] <= a < incl[e]. Larger rows get the whole wavefront each.
+// degree <= T1 are expanded packed: their arcs are numbered consecutively in
+// lane order and taken 64 x kLbsUnroll at a time, one arc per lane per window.
+// A lane finds the row of its arc from the row starts that fall inside the
+// span: each row writes its lane into a per-wavefront byte map at its first
+// arc, a ballot over the map gives the window's start positions, and the
+// last start at or before the lane names the row (or, with none, the row that
+// was open at the end of the previous window). Larger rows get the whole
+// wavefront each.
 template <typename OffT, bool kAtomic>
 __device__ __forceinline__ void process_batch(const SingleParams& p, int32_t u, bool valid, int lane, int lvl,
-                                              unsigned long long& arcs, uint32_t* hot, uint32_t hot_limit) {
+                                              unsigned long long& arcs, uint32_t* hot, uint32_t hot_limit,
+                                              uint8_t* starts) {
+    static_assert(kLbsUnroll == 4, "the start map is cleared one 32-bit word per lane");
+    constexpr int SPAN = 64 * kLbsUnroll;
     int64_t beg = 0, d = 0;
     int32_t uo = 0;  // the row as a caller id: the parent of its discoveries
     if (valid) {
@@ -270,28 +290,28 @@ __device__ __forceinline__ void process_batch(const SingleParams& p, int32_t u, 
     const int incl = wave_incl_scan(ds, lane);
     const int excl = incl - ds;
     const int total = __shfl(incl, 63, 64);
-    for (int base = 0; base < total; base += 64 * kLbsUnroll) {
+    const int64_t rbase = beg - excl;  // column index of packed arc a of this row: rbase + a
+    int open = 0;                      // row holding the arc just before the current window
+    for (int base = 0; base < total; base += SPAN) {
+        reinterpret_cast<uint32_t*>(starts)[lane] = 0xFFFFFFFFu;
+        __builtin_amdgcn_wave_barrier();
+        if (ds > 0 && excl >= base && excl < base + SPAN) starts[excl - base] = (uint8_t)lane;
+        __builtin_amdgcn_wave_barrier();
         int64_t pos[kLbsUnroll];
         bool ok[kLbsUnroll];
         int32_t par[kLbsUnroll];
 #pragma unroll
         for (int i = 0; i < kLbsUnroll; ++i) {
-            const int a = base + i * 64 + lane;
-            ok[i] = a < total;
-            const int ac = ok[i] ? a : total - 1;
-            int lo = 0, hi = 63;
-#pragma unroll
-            for (int s = 0; s < 6; ++s) {
-                const int mid = (lo + hi) >> 1;
-                if (__shfl(incl, mid, 64) > ac)
-                    hi = mid;
-                else
-                    lo = mid + 1;
-            }
-            const int ex = __shfl(excl, lo, 64);
-            const int64_t b = shfl64(beg, lo);
-            par[i] = __shfl(uo, lo, 64);
-            pos[i] = b + (ac - ex);
+            const int here = starts[i * 64 + lane];
+            const uint64_t m = __ballot(here != 0xFF) & ((2ull << lane) - 1ull);  // starts at or before this lane
+            const int last = m ? 63 - __builtin_clzll(m) : 0;
+            const int from_map = __shfl(here, last, 64);
+            const int e = m ? from_map : open;
+            open = __shfl(e, 63, 64);
+            ok[i] = base + i * 64 + lane < total;
+            const int ec = ok[i] ? e : 0;
+            pos[i] = shfl64(rbase, ec) + (base + i * 64 + lane);
+            par[i] = __shfl(uo, ec, 64);
         }
         visit_arcs<kAtomic, kLbsUnroll>(p, pos, ok, par, lvl, hot, hot_limit);
     }
@@ -311,6 +331,7 @@ struct ExpandShared {
         struct {
             uint32_t ring[NW][128];    // staged frontier (or unvisited) vertices, one ring per wavefront
             uint32_t bu_bits[NW][64];  // bottom-up: new visited bits of each wavefront's 64-word window
+            uint8_t starts[NW][64 * kLbsUnroll];  // packed rows: lane of the row starting at each arc of a span
         } w;
         struct {
             uint32_t segpre[kMaxRestoreGrid + 1];  // exclusive prefix of segment arcs
@@ -330,13 +351,15 @@ struct ExpandShared {
 
 // Rows above T2: this workgroup's share [a0, a1) of the level's concatenated
 // big-row arcs. Row metadata is staged BLOCK rows at a time (every thread loads
-// one row), then every thread takes kBigUnroll arcs per step and finds its row
-// by binary search over the staged starts: all lanes stay busy whatever the
-// row lengths, and no thread walks rows serially.
+// one row); each wavefront then takes a contiguous run of those arcs, 64 x
+// kBigUnroll consecutive arcs per step, so column reads are coalesced and a
+// lane finds its row by moving a cursor forward over the staged starts (rows
+// above T2 are long, so the cursor seldom moves) instead of searching anew.
 template <typename OffT, bool kAtomic, int BLOCK>
 __device__ __forceinline__ void expand_big(const SingleParams& p, ExpandShared<BLOCK>& sh, int64_t a0, int64_t a1,
                                            int lvl, unsigned long long& arcs, uint32_t* hot, uint32_t hot_limit) {
-    const int tid = threadIdx.x;
+    constexpr int NW = BLOCK / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int R = p.restore_grid;
     constexpr int PER_T = (kMaxRestoreGrid + BLOCK) / BLOCK;  // covers entries 0..R inclusive
     // Prefix sums over the segments (one per restore block): arcs and rows.
@@ -420,24 +443,35 @@ __device__ __forceinline__ void expand_big(const SingleParams& p, ExpandShared<B
         if (tid == nt - 1) sh.staged_end = end;
         __syncthreads();
         const int64_t hi_arc = sh.staged_end;
-        for (int64_t b = from; b < hi_arc; b += (int64_t)BLOCK * kBigUnroll) {
-            int64_t pos[kBigUnroll];
-            bool ok[kBigUnroll];
-            int32_t par[kBigUnroll];
-#pragma unroll
-            for (int i = 0; i < kBigUnroll; ++i) {
-                const int64_t a = b + (int64_t)i * BLOCK + tid;
-                ok[i] = a < hi_arc;
-                int lo = 0, hi = nt - 1;  // last staged row starting at or before a
-#pragma unroll
-                for (int st_ = 0; st_ < 31 - __builtin_clz(BLOCK); ++st_) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (sh.x.big.start[mid] <= a) lo = mid; else hi = mid - 1;
-                }
-                pos[i] = sh.x.big.base[lo] + a;
-                par[i] = sh.x.big.u[lo];
+        // Each wavefront takes a contiguous run of the staged arcs and walks
+        // the staged rows with a cursor: a lane's row only moves forward.
+        const int64_t per_w = ((hi_arc - from + NW - 1) / NW + 63) & ~(int64_t)63;
+        const int64_t w_lo = from + (int64_t)wid * per_w;
+        const int64_t w_hi = w_lo + per_w < hi_arc ? w_lo + per_w : hi_arc;
+        if (w_lo < w_hi) {
+            int lo = 0, hi = nt - 1;  // last staged row starting at or before w_lo
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (sh.x.big.start[mid] <= w_lo) lo = mid; else hi = mid - 1;
             }
-            visit_arcs<kAtomic, kBigUnroll>(p, pos, ok, par, lvl, hot, hot_limit);
+            int row = lo;
+            for (int64_t ws = w_lo; ws < w_hi; ws += 64 * kBigUnroll) {
+                int64_t pos[kBigUnroll];
+                bool ok[kBigUnroll];
+                int32_t par[kBigUnroll];
+                int r = row;
+#pragma unroll
+                for (int i = 0; i < kBigUnroll; ++i) {
+                    const int64_t a = ws + i * 64 + lane;
+                    ok[i] = a < w_hi;
+                    const int64_t ac = ok[i] ? a : w_hi - 1;
+                    while (r + 1 < nt && sh.x.big.start[r + 1] <= ac) ++r;
+                    pos[i] = sh.x.big.base[r] + ac;
+                    par[i] = sh.x.big.u[r];
+                }
+                row = __shfl(r, 63, 64);
+                visit_arcs<kAtomic, kBigUnroll>(p, pos, ok, par, lvl, hot, hot_limit);
+            }
         }
         if (tid == 0) arcs += (unsigned long long)(hi_arc - from);
         from = hi_arc;
@@ -555,41 +589,48 @@ template <typename OffT, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_init(SingleParams p, int nslots) {
     const int64_t gtid = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
     const int64_t gsize = (int64_t)gridDim.x * BLOCK;
-    const int64_t n4 = p.n / 4;
-    // Caller outputs (caller ids), and on the degree-ordered copy also the
-    // run's own level array.
     const int ro = p.root_out;
-    const bool aligned = ((reinterpret_cast<uintptr_t>(p.out_lv) | reinterpret_cast<uintptr_t>(p.out_pa) |
-                           reinterpret_cast<uintptr_t>(p.lv)) & 15) == 0;
-    if (aligned) {
-        int4* lv4 = reinterpret_cast<int4*>(p.out_lv);
-        int4* pa4 = reinterpret_cast<int4*>(p.out_pa);
-        int4* in4 = reinterpret_cast<int4*>(p.lv);
-        for (int64_t i = gtid; i < n4; i += gsize) {
-            int4 a = make_int4(-1, -1, -1, -1), b = make_int4(-1, -1, -1, -1), c = make_int4(-1, -1, -1, -1);
-            if ((ro >> 2) == i) {
-                const int k = ro & 3;
-                if (k == 0) { a.x = 0; b.x = ro; }
-                if (k == 1) { a.y = 0; b.y = ro; }
-                if (k == 2) { a.z = 0; b.z = ro; }
-                if (k == 3) { a.w = 0; b.w = ro; }
+    if (p.new2old) {
+        // Degree-ordered copy: the run's {level, parent} records (the caller's
+        // arrays are written after the last level). Two records per 16 bytes.
+        int4* r4 = reinterpret_cast<int4*>(p.lv);
+        const int64_t n2 = p.n / 2;
+        for (int64_t i = gtid; i < n2; i += gsize) {
+            int4 x = make_int4(-1, -1, -1, -1);
+            if ((p.root >> 1) == i) {
+                if (p.root & 1) { x.z = 0; x.w = ro; } else { x.x = 0; x.y = ro; }
             }
-            if ((p.root >> 2) == i) {
-                const int k = p.root & 3;
-                if (k == 0) c.x = 0;
-                if (k == 1) c.y = 0;
-                if (k == 2) c.z = 0;
-                if (k == 3) c.w = 0;
-            }
-            lv4[i] = a;
-            pa4[i] = b;
-            if (p.new2old) in4[i] = c;
+            r4[i] = x;
         }
-    }
-    for (int64_t i = (aligned ? n4 * 4 : 0) + gtid; i < p.n; i += gsize) {
-        p.out_lv[i] = (i == ro) ? 0 : -1;
-        p.out_pa[i] = (i == ro) ? ro : -1;
-        if (p.new2old) p.lv[i] = (i == p.root) ? 0 : -1;
+        if ((p.n & 1) && gtid == 0) {
+            const int64_t v = p.n - 1;
+            p.lv[2 * v] = (v == p.root) ? 0 : -1;
+            p.lv[2 * v + 1] = (v == p.root) ? ro : -1;
+        }
+    } else {
+        // The caller's levels and parents (caller ids).
+        const int64_t n4 = p.n / 4;
+        const bool aligned = ((reinterpret_cast<uintptr_t>(p.out_lv) | reinterpret_cast<uintptr_t>(p.out_pa)) & 15) == 0;
+        if (aligned) {
+            int4* lv4 = reinterpret_cast<int4*>(p.out_lv);
+            int4* pa4 = reinterpret_cast<int4*>(p.out_pa);
+            for (int64_t i = gtid; i < n4; i += gsize) {
+                int4 a = make_int4(-1, -1, -1, -1), b = make_int4(-1, -1, -1, -1);
+                if ((ro >> 2) == i) {
+                    const int k = ro & 3;
+                    if (k == 0) { a.x = 0; b.x = ro; }
+                    if (k == 1) { a.y = 0; b.y = ro; }
+                    if (k == 2) { a.z = 0; b.z = ro; }
+                    if (k == 3) { a.w = 0; b.w = ro; }
+                }
+                lv4[i] = a;
+                pa4[i] = b;
+            }
+        }
+        for (int64_t i = (aligned ? n4 * 4 : 0) + gtid; i < p.n; i += gsize) {
+            p.out_lv[i] = (i == ro) ? 0 : -1;
+            p.out_pa[i] = (i == ro) ? ro : -1;
+        }
     }
     const int64_t rw = p.root >> 5;
     const uint32_t rb = 1u << (p.root & 31);
@@ -636,6 +677,20 @@ __global__ __launch_bounds__(BLOCK) void k_init(SingleParams p, int nslots) {
         p.ctrl->dir[1] = 0;
         p.ctrl->visited[0] = 0;
         p.ctrl->visited[1] = 0;
+    }
+}
+
+// After the last level on the degree-ordered copy: the caller's levels and
+// parents from the run's records, in run order (reads coalesced; cold ids keep
+// the caller's order, so the writes are nearly coalesced too).
+__global__ __launch_bounds__(256) void k_out(const int2* rec, const int32_t* new2old, int32_t* out_lv,
+                                             int32_t* out_pa, int64_t n) {
+    const int64_t gsize = (int64_t)gridDim.x * 256;
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < n; v += gsize) {
+        const int2 r = rec[v];
+        const int32_t o = new2old[v];
+        out_lv[o] = r.x;
+        out_pa[o] = r.y;
     }
 }
 
@@ -762,7 +817,7 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl) {
             if (tail - head >= 64) {
                 const int32_t u = (int32_t)sh.x.w.ring[wid][(head + lane) & 127];
                 head += 64;
-                process_batch<OffT, kAtomic>(p, u, true, lane, lvl + 1, arcs, hot_lds, hot_limit);
+                process_batch<OffT, kAtomic>(p, u, true, lane, lvl + 1, arcs, hot_lds, hot_limit, sh.x.w.starts[wid]);
             }
         }
     }
@@ -770,7 +825,7 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl) {
         const int cnt = (int)(tail - head);
         const bool valid = lane < cnt;
         const int32_t u = valid ? (int32_t)sh.x.w.ring[wid][(head + lane) & 127] : 0;
-        process_batch<OffT, kAtomic>(p, u, valid, lane, lvl + 1, arcs, hot_lds, hot_limit);
+        process_batch<OffT, kAtomic>(p, u, valid, lane, lvl + 1, arcs, hot_lds, hot_limit, sh.x.w.starts[wid]);
     }
 
     // ---- block total of scanned arcs (plain update of this block's own slot)
@@ -830,7 +885,7 @@ __global__ __launch_bounds__(kRestoreBlock) void k_restore(SingleParams p, int l
                 const int src = lane < 32 ? wa : wb;
                 const int64_t v = (wave_w0 + src) * 32 + (lane & 31);
                 const bool okl = src >= 0 && v < p.n;
-                const int lvv = okl ? ld(p.lv + v) : -1;
+                const int lvv = okl ? ld(p.lv + lv_at(p, v)) : -1;
                 const uint64_t m = __ballot(lvv == next);
                 if (lane == wa) exact = (uint32_t)m;
                 if (lane == wb) exact = (uint32_t)(m >> 32);
@@ -1107,6 +1162,11 @@ void launch_typed(bfs_graph* g, const bfs_tunables& t, Workspace* w, SingleParam
         if (w->host_ctrl->done || lvl > p.n + 1) break;
         chunk = chunk < 64 ? chunk * 2 : 64;
     }
+    if (p.new2old) {
+        const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((p.n + 255) / 256, (int64_t)g->cu_count * 16));
+        k_out<<<blocks, 256, 0, s>>>(reinterpret_cast<const int2*>(p.lv), p.new2old, p.out_lv, p.out_pa, p.n);
+        BFS_HIP(hipGetLastError());
+    }
 }
 
 }  // namespace
@@ -1121,7 +1181,8 @@ void launch_single(bfs_graph* g, const bfs_tunables& t, Workspace* w, int32_t ro
     const int32_t want_hot = hot_count(g, t);
     const HotLayout* h = want_hot > 0 ? g->hot.get() : nullptr;
     if (want_hot > 0 && (!h || h->hot != want_hot)) fail(BFS_E_INTERNAL, "degree-ordered copy out of date");
-    if (h && !w->lv_new) fail(BFS_E_INTERNAL, "workspace lacks the level array of the copy");
+    if (h && (!w->run_rec || (reinterpret_cast<uintptr_t>(w->run_rec) & 15) != 0))
+        fail(BFS_E_INTERNAL, "workspace lacks the run records of the copy");
     const BigTable& bt = h ? h->big : g->big;
     if (bt.threshold != t.wave_max_degree) fail(BFS_E_INTERNAL, "big-row table out of date");
     SingleParams p{};
@@ -1131,7 +1192,7 @@ void launch_single(bfs_graph* g, const bfs_tunables& t, Workspace* w, int32_t ro
     p.root = h ? h->old2new[(size_t)root] : root;
     p.root_out = root;
     p.words = w->words;
-    p.lv = h ? w->lv_new : levels;
+    p.lv = h ? w->run_rec : levels;
     p.out_lv = levels;
     p.out_pa = parents;
     p.new2old = h ? h->d_new2old : nullptr;
@@ -1217,17 +1278,14 @@ void validate_device_csr(const void* off, bool off32, const int32_t* col, int64_
 
 void launch_single_stats_from_levels(bfs_graph* g, const bfs_tunables& t, Workspace* w, const int32_t* levels,
                                      hipStream_t s) {
-    const bool copy = hot_count(g, t) > 0;
-    const int32_t* lv = copy ? w->lv_new : levels;
-    if (!lv) fail(BFS_E_INTERNAL, "no level array for the stats");
+    (void)t;  // the caller's levels are complete on either layout
+    if (!levels) fail(BFS_E_INTERNAL, "no level array for the stats");
     BFS_HIP(hipMemsetAsync(&w->ctrl->reached, 0, 2 * sizeof(unsigned long long), s));
     const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((g->n + 255) / 256, (int64_t)g->cu_count * 8));
-    if (copy)
-        k_stats_levels<int64_t><<<blocks, 256, 0, s>>>(lv, g->hot->d_off, g->n, w->ctrl);
-    else if (g->off32)
-        k_stats_levels<int32_t><<<blocks, 256, 0, s>>>(lv, static_cast<const int32_t*>(g->d_off), g->n, w->ctrl);
+    if (g->off32)
+        k_stats_levels<int32_t><<<blocks, 256, 0, s>>>(levels, static_cast<const int32_t*>(g->d_off), g->n, w->ctrl);
     else
-        k_stats_levels<int64_t><<<blocks, 256, 0, s>>>(lv, static_cast<const int64_t*>(g->d_off), g->n, w->ctrl);
+        k_stats_levels<int64_t><<<blocks, 256, 0, s>>>(levels, static_cast<const int64_t*>(g->d_off), g->n, w->ctrl);
     BFS_HIP(hipGetLastError());
 }
 

@@ -106,6 +106,14 @@ typedef struct {
                                    degree-ordered copy of the graph) in LDS during levels with
                                    large frontiers and probes them there first; rounded up to
                                    a multiple of 2048; -1 = off, 0 = library default */
+    int32_t lds_visited;        /* single-root runs without the degree-ordered copy: every
+                                   workgroup copies the whole visited bitmap (bottom-up levels:
+                                   the whole frontier bitmap) into LDS at the start of a level
+                                   with a large frontier and probes it there first. 1 = on
+                                   (BFS_E_INVALID_ARG from bfs_graph_set_tunables if the bitmap
+                                   does not fit in LDS beside the workgroup), -1 = off, 0 =
+                                   library default (on for 2^16..2^20 vertices, with 1024-thread
+                                   workgroups) */
 } bfs_tunables;
 
 /* ---- graph residency ------------------------------------------------------ */

@@ -195,6 +195,11 @@ void free_hot_layout(bfs_graph* g);
 void launch_relabel_cols(const bfs_graph* g, const int64_t* d_noff, const int32_t* d_new2old,
                          const int32_t* d_old2new, int32_t* d_ncol, int32_t hot);
 int64_t padded_words(int64_t n);
+// Most visited-bitmap words an expansion workgroup of `block` threads can hold
+// in LDS beside its static shared memory.
+int64_t lds_visited_words_max(int block);
+// Visited-bitmap words a single-root run keeps in LDS (0 = none).
+int64_t lds_visited_words(const bfs_graph* g, const bfs_tunables& t);
 // Blocks of the restore pass: 256-word chunks, chunk c handled by block c % grid.
 constexpr int kRestoreBlock = 256;
 // Upper bound of the restore grid (= number of big-row list segments); the

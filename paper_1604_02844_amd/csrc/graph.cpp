@@ -238,7 +238,15 @@ void build_hot_layout(bfs_graph* g, int32_t hot, int32_t threshold) {
     g->hot = std::move(h);
 }
 
+int64_t lds_visited_words(const bfs_graph* g, const bfs_tunables& t) {
+    if (t.lds_visited <= 0 || hot_count(g, t) > 0) return 0;
+    const int64_t words = padded_words(g->n);
+    return words <= lds_visited_words_max(t.block_size) ? words : 0;
+}
+
 void apply_tunables(bfs_graph* g, const bfs_tunables& r) {
+    if (r.lds_visited > 0 && hot_count(g, r) == 0 && padded_words(g->n) > lds_visited_words_max(r.block_size))
+        fail(BFS_E_INVALID_ARG, "the visited bitmap does not fit in LDS beside this workgroup size");
     const int32_t want_hot = hot_count(g, r);
     const bool big_stale = r.wave_max_degree != g->big.threshold;
     const bool hot_stale = want_hot != (g->hot ? g->hot->hot : 0) ||
@@ -275,7 +283,7 @@ void apply_tunables(bfs_graph* g, const bfs_tunables& r) {
 bfs_tunables default_tunables(const bfs_graph* g) {
     bfs_tunables t{};
     (void)g;
-    t.small_max_degree = 32;
+    t.small_max_degree = 256;
     t.wave_max_degree = 256;
     t.chunk_arcs = 0;
     t.block_size = 256;
@@ -290,6 +298,12 @@ bfs_tunables default_tunables(const bfs_graph* g) {
                        g->max_degree > 64 * std::max<int64_t>(1, g->nnz / std::max<int64_t>(1, g->n));
     t.hot_vertices = large ? 1 << 19 : -1;
     if (large) t.block_size = 1024;
+    // Up to 2^20 vertices the whole visited bitmap (128 KiB) fits in the LDS
+    // of a 1024-thread workgroup instead.
+    const bool fits = g && !large && g->n >= (int64_t)1 << 16 &&
+                      padded_words(g->n) <= lds_visited_words_max(1024);
+    t.lds_visited = fits ? 1 : -1;
+    if (fits) t.block_size = 1024;
     return t;
 }
 
@@ -305,6 +319,10 @@ bfs_tunables resolve_tunables(const bfs_graph* g, const bfs_tunables& in) {
     if (t.blocks_per_cu < 0) t.blocks_per_cu = 0;
     if (t.batch_width <= 0 || t.batch_width > 64) t.batch_width = d.batch_width;
     if (t.update_mode != 1 && t.update_mode != 2) t.update_mode = d.update_mode;
+    // By default the LDS copy of the visited bitmap goes with 1024-thread
+    // workgroups only: with fewer waves per copy it costs occupancy.
+    if (t.lds_visited == 0) t.lds_visited = d.lds_visited > 0 && t.block_size == 1024 ? 1 : -1;
+    t.lds_visited = t.lds_visited > 0 ? 1 : -1;
     if (t.hot_vertices == 0) t.hot_vertices = d.hot_vertices;
     if (t.hot_vertices < 0) t.hot_vertices = -1;
     if (t.hot_vertices > kMaxHotWords * 32) t.hot_vertices = kMaxHotWords * 32;

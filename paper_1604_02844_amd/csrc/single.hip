@@ -94,7 +94,10 @@ struct SingleParams {
     uint32_t* hot_vis;
     uint32_t* hot_fr;          // compact bitmap of the hot vertices in the frontier (exact per level)
     int32_t hot_words;         // words of hot_vis / hot_fr (0 = off)
-    int64_t hot_min_frontier;  // use the LDS copy only for frontiers of at least this many vertices
+    int64_t hot_min_frontier;  // use an LDS copy only for frontiers of at least this many vertices
+    // Without the degree-ordered copy: words of the visited bitmap (bottom-up
+    // levels: of the frontier bitmap) that workgroups copy whole into LDS (0 = off).
+    int32_t full_words;
     int64_t nnz;
     int32_t hybrid;            // levels with large frontiers may run bottom-up (symmetric graphs)
 };
@@ -190,23 +193,44 @@ __device__ __forceinline__ void record(const SingleParams& p, int32_t v, int lvl
     }
 }
 
+// A workgroup's LDS copy of visited bits, taken at the start of a level (so a
+// set bit is final): either the compact bits of the hot ids 32r, r <
+// hot_limit (bit r), or the first full_words words of the visited bitmap
+// itself (bit v). Neither when both limits are 0.
+struct LdsVis {
+    uint32_t* bits;
+    uint32_t hot_limit;
+    uint32_t full_words;
+};
+
+// Bit of vertex v in the LDS copy, if the copy holds it.
+__device__ __forceinline__ bool lds_slot(const LdsVis& l, int32_t v, uint32_t& bit) {
+    const uint32_t r = (uint32_t)v >> 5;
+    if (l.full_words) {
+        bit = (uint32_t)v;
+        return r < l.full_words;
+    }
+    bit = r;
+    return (v & 31) == 0 && r < l.hot_limit;
+}
+
 // Hot ids (32r with r < hot_limit) are first looked up in the workgroup's LDS
 // copy of the compact hot bitmap (taken at the start of the level, so a set bit
 // is final); only the rest, and hot ids not yet visited, probe the global bitmap.
 template <bool kAtomic, int U>
 __device__ __forceinline__ void visit_arcs(const SingleParams& p, const int64_t (&pos)[U], const bool (&ok)[U],
-                                           const int32_t (&par)[U], int lvl, uint32_t* hot, uint32_t hot_limit) {
+                                           const int32_t (&par)[U], int lvl, const LdsVis& lds) {
     int32_t v[U];
 #pragma unroll
     for (int i = 0; i < U; ++i) v[i] = ok[i] ? __builtin_nontemporal_load(p.col + pos[i]) : 0;
     uint32_t w[U];
-    bool in_hot[U];
+    bool in_lds[U];
+    uint32_t slot[U];
 #pragma unroll
     for (int i = 0; i < U; ++i) {
-        const uint32_t r = (uint32_t)v[i] >> 5;
-        in_hot[i] = ok[i] && (v[i] & 31) == 0 && r < hot_limit;
-        const bool known = in_hot[i] && ((hot[r >> 5] >> (r & 31)) & 1u);
-        w[i] = (ok[i] && !known) ? p.vis[r] : ~0u;
+        in_lds[i] = ok[i] && lds_slot(lds, v[i], slot[i]);
+        const bool known = in_lds[i] && ((lds.bits[slot[i] >> 5] >> (slot[i] & 31)) & 1u);
+        w[i] = (ok[i] && !known) ? p.vis[(uint32_t)v[i] >> 5] : ~0u;
     }
     if (kAtomic) {
         uint32_t old[U];
@@ -222,7 +246,7 @@ __device__ __forceinline__ void visit_arcs(const SingleParams& p, const int64_t 
         for (int i = 0; i < U; ++i) {
             const uint32_t b = 1u << (v[i] & 31);
             if (need[i] && !(old[i] & b)) record(p, v[i], lvl, par[i]);
-            if (need[i] && in_hot[i]) atomicOr(hot + (v[i] >> 10), 1u << ((v[i] >> 5) & 31));
+            if (need[i] && in_lds[i]) atomicOr(lds.bits + (slot[i] >> 5), 1u << (slot[i] & 31));
         }
     } else {
         // The plain load above is only a filter: its line may be stale in this
@@ -239,14 +263,14 @@ __device__ __forceinline__ void visit_arcs(const SingleParams& p, const int64_t 
                 p.vis[v[i] >> 5] = w[i] | b;  // may lose a concurrent update: restored later
                 record(p, v[i], lvl, par[i]);
             }
-            if (!(w[i] & b) && in_hot[i]) atomicOr(hot + (v[i] >> 10), 1u << ((v[i] >> 5) & 31));  // this workgroup's later probes
+            if (!(w[i] & b) && in_lds[i]) atomicOr(lds.bits + (slot[i] >> 5), 1u << (slot[i] & 31));  // this workgroup's later probes
         }
     }
 }
 
 template <bool kAtomic, int U>
 __device__ __forceinline__ void expand_row(const SingleParams& p, int64_t beg, int64_t d, int32_t u, int t,
-                                           int nthreads, int lvl, uint32_t* hot, uint32_t hot_limit) {
+                                           int nthreads, int lvl, const LdsVis& lds) {
     for (int64_t j0 = 0; j0 < d; j0 += (int64_t)nthreads * U) {
         int64_t pos[U];
         bool ok[U];
@@ -258,7 +282,7 @@ __device__ __forceinline__ void expand_row(const SingleParams& p, int64_t beg, i
             pos[i] = beg + j;
             par[i] = u;
         }
-        visit_arcs<kAtomic, U>(p, pos, ok, par, lvl, hot, hot_limit);
+        visit_arcs<kAtomic, U>(p, pos, ok, par, lvl, lds);
     }
 }
 
@@ -273,10 +297,10 @@ __device__ __forceinline__ void expand_row(const SingleParams& p, int64_t beg, i
 // wavefront each.
 template <typename OffT, bool kAtomic>
 __device__ __forceinline__ void process_batch(const SingleParams& p, int32_t u, bool valid, int lane, int lvl,
-                                              unsigned long long& arcs, uint32_t* hot, uint32_t hot_limit,
+                                              unsigned long long& arcs, const LdsVis& lds,
                                               uint8_t* starts) {
-    static_assert(kLbsUnroll == 4, "the start map is cleared one 32-bit word per lane");
     constexpr int SPAN = 64 * kLbsUnroll;
+    static_assert(SPAN % 256 == 0, "the start map is cleared in 32-bit words, one or more per lane");
     int64_t beg = 0, d = 0;
     int32_t uo = 0;  // the row as a caller id: the parent of its discoveries
     if (valid) {
@@ -293,7 +317,8 @@ __device__ __forceinline__ void process_batch(const SingleParams& p, int32_t u, 
     const int64_t rbase = beg - excl;  // column index of packed arc a of this row: rbase + a
     int open = 0;                      // row holding the arc just before the current window
     for (int base = 0; base < total; base += SPAN) {
-        reinterpret_cast<uint32_t*>(starts)[lane] = 0xFFFFFFFFu;
+#pragma unroll
+        for (int k = 0; k < SPAN / 256; ++k) reinterpret_cast<uint32_t*>(starts)[k * 64 + lane] = 0xFFFFFFFFu;
         __builtin_amdgcn_wave_barrier();
         if (ds > 0 && excl >= base && excl < base + SPAN) starts[excl - base] = (uint8_t)lane;
         __builtin_amdgcn_wave_barrier();
@@ -313,14 +338,13 @@ __device__ __forceinline__ void process_batch(const SingleParams& p, int32_t u, 
             pos[i] = shfl64(rbase, ec) + (base + i * 64 + lane);
             par[i] = __shfl(uo, ec, 64);
         }
-        visit_arcs<kAtomic, kLbsUnroll>(p, pos, ok, par, lvl, hot, hot_limit);
+        visit_arcs<kAtomic, kLbsUnroll>(p, pos, ok, par, lvl, lds);
     }
     uint64_t mm = __ballot(valid && !small && d > 0);
     while (mm) {
         const int e = __builtin_ctzll(mm);
         mm &= mm - 1;
-        expand_row<kAtomic, kUnroll>(p, shfl64(beg, e), shfl64(d, e), __shfl(uo, e, 64), lane, 64, lvl, hot,
-                                     hot_limit);
+        expand_row<kAtomic, kUnroll>(p, shfl64(beg, e), shfl64(d, e), __shfl(uo, e, 64), lane, 64, lvl, lds);
     }
 }
 
@@ -357,7 +381,7 @@ struct ExpandShared {
 // above T2 are long, so the cursor seldom moves) instead of searching anew.
 template <typename OffT, bool kAtomic, int BLOCK>
 __device__ __forceinline__ void expand_big(const SingleParams& p, ExpandShared<BLOCK>& sh, int64_t a0, int64_t a1,
-                                           int lvl, unsigned long long& arcs, uint32_t* hot, uint32_t hot_limit) {
+                                           int lvl, unsigned long long& arcs, const LdsVis& lds) {
     constexpr int NW = BLOCK / 64;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int R = p.restore_grid;
@@ -470,7 +494,7 @@ __device__ __forceinline__ void expand_big(const SingleParams& p, ExpandShared<B
                     par[i] = sh.x.big.u[r];
                 }
                 row = __shfl(r, 63, 64);
-                visit_arcs<kAtomic, kBigUnroll>(p, pos, ok, par, lvl, hot, hot_limit);
+                visit_arcs<kAtomic, kBigUnroll>(p, pos, ok, par, lvl, lds);
             }
         }
         if (tid == 0) arcs += (unsigned long long)(hi_arc - from);
@@ -490,14 +514,15 @@ __device__ __forceinline__ void expand_big(const SingleParams& p, ExpandShared<B
 // device-scope loads: another XCD wrote it in the previous launch.
 template <typename OffT, int BLOCK>
 __device__ __forceinline__ void bottom_up(const SingleParams& p, ExpandShared<BLOCK>& sh, int lvl,
-                                          const uint32_t* hot, uint32_t hot_limit, bool cold_empty) {
-    // Is u in the frontier? Hot ids from the LDS copy of the frontier's hot
-    // bits; others from the frontier bitmap, unless the frontier has none.
+                                          const LdsVis& lds, bool cold_empty) {
+    // Is u in the frontier? From the LDS copy of the frontier's bits (hot ids,
+    // or whole words) where it holds u; otherwise from the frontier bitmap,
+    // unless the frontier has no vertex outside the hot set.
     auto in_frontier = [&](int32_t u) -> bool {
-        const uint32_t r = (uint32_t)u >> 5;
-        if ((u & 31) == 0 && r < hot_limit) return (hot[r >> 5] >> (r & 31)) & 1u;
+        uint32_t bit;
+        if (lds_slot(lds, u, bit)) return (lds.bits[bit >> 5] >> (bit & 31)) & 1u;
         if (cold_empty) return false;
-        return (ld(p.fr + r) >> (u & 31)) & 1u;
+        return (ld(p.fr + ((uint32_t)u >> 5)) >> (u & 31)) & 1u;
     };
     constexpr int NW = BLOCK / 64;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -749,7 +774,7 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl) {
             // LDS copy of the frontier's hot bits, and whether the frontier has
             // any vertex outside the hot set.
             extern __shared__ uint32_t hot_lds[];
-            uint32_t hlim = 0;
+            LdsVis lds{hot_lds, 0u, 0u};
             bool cold_empty = false;
             if (p.hot_words > 0) {
                 const unsigned long long* src = reinterpret_cast<const unsigned long long*>(p.hot_fr);
@@ -766,22 +791,36 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl) {
                 unsigned long long hot_in = 0;
                 for (int i = 0; i < NW; ++i) hot_in += sh.red[i];
                 cold_empty = hot_in == sh.found;
-                hlim = (uint32_t)p.hot_words * 32u;
+                lds.hot_limit = (uint32_t)p.hot_words * 32u;
+                __syncthreads();
+            } else if (p.full_words > 0) {
+                // The whole frontier bitmap.
+                const unsigned long long* src = reinterpret_cast<const unsigned long long*>(p.fr);
+                unsigned long long* dst = reinterpret_cast<unsigned long long*>(hot_lds);
+                for (int i = tid; i < p.full_words / 2; i += BLOCK) dst[i] = ld(src + i);
+                lds.full_words = (uint32_t)p.full_words;
                 __syncthreads();
             }
-            bottom_up<OffT, BLOCK>(p, sh, lvl, hot_lds, hlim, cold_empty);
+            bottom_up<OffT, BLOCK>(p, sh, lvl, lds, cold_empty);
             return;
         }
     }
 
-    // ---- LDS copy of the compact hot bitmap (exact at level start)
+    // ---- LDS copy of visited bits (exact at level start): the compact hot
+    // bitmap on the degree-ordered copy, else the whole visited snapshot
     extern __shared__ uint32_t hot_lds[];
-    uint32_t hot_limit = 0;
+    LdsVis lds{hot_lds, 0u, 0u};
     if (p.hot_words > 0 && (int64_t)sh.found >= p.hot_min_frontier) {
         const unsigned long long* src = reinterpret_cast<const unsigned long long*>(p.hot_vis);
         unsigned long long* dst = reinterpret_cast<unsigned long long*>(hot_lds);
         for (int i = tid; i < p.hot_words / 2; i += BLOCK) dst[i] = ld(src + i);
-        hot_limit = (uint32_t)p.hot_words * 32u;
+        lds.hot_limit = (uint32_t)p.hot_words * 32u;
+        __syncthreads();
+    } else if (p.full_words > 0 && (int64_t)sh.found >= p.hot_min_frontier) {
+        const unsigned long long* src = reinterpret_cast<const unsigned long long*>(p.vis_prev);
+        unsigned long long* dst = reinterpret_cast<unsigned long long*>(hot_lds);
+        for (int i = tid; i < p.full_words / 2; i += BLOCK) dst[i] = ld(src + i);
+        lds.full_words = (uint32_t)p.full_words;
         __syncthreads();
     }
 
@@ -791,7 +830,7 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl) {
         if (per < p.min_share) per = p.min_share;
         const int64_t a0 = bid * per;
         const int64_t a1 = a0 + per < ta ? a0 + per : ta;
-        if (a0 < a1) expand_big<OffT, kAtomic, BLOCK>(p, sh, a0, a1, lvl + 1, arcs, hot_lds, hot_limit);
+        if (a0 < a1) expand_big<OffT, kAtomic, BLOCK>(p, sh, a0, a1, lvl + 1, arcs, lds);
     }
 
     // ---- every other frontier vertex: a contiguous run of words per wavefront
@@ -817,7 +856,7 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl) {
             if (tail - head >= 64) {
                 const int32_t u = (int32_t)sh.x.w.ring[wid][(head + lane) & 127];
                 head += 64;
-                process_batch<OffT, kAtomic>(p, u, true, lane, lvl + 1, arcs, hot_lds, hot_limit, sh.x.w.starts[wid]);
+                process_batch<OffT, kAtomic>(p, u, true, lane, lvl + 1, arcs, lds, sh.x.w.starts[wid]);
             }
         }
     }
@@ -825,7 +864,7 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl) {
         const int cnt = (int)(tail - head);
         const bool valid = lane < cnt;
         const int32_t u = valid ? (int32_t)sh.x.w.ring[wid][(head + lane) & 127] : 0;
-        process_batch<OffT, kAtomic>(p, u, valid, lane, lvl + 1, arcs, hot_lds, hot_limit, sh.x.w.starts[wid]);
+        process_batch<OffT, kAtomic>(p, u, valid, lane, lvl + 1, arcs, lds, sh.x.w.starts[wid]);
     }
 
     // ---- block total of scanned arcs (plain update of this block's own slot)
@@ -1119,15 +1158,15 @@ int lds_dynamic_cap() {
 
 
 template <typename OffT, int BLOCK, bool kAtomic>
-Grids grids_for(bfs_graph* g, const bfs_tunables& t, int64_t nslots, int hot_words) {
+Grids grids_for(bfs_graph* g, const bfs_tunables& t, int64_t nslots, int lds_words) {
     // Dynamic LDS (the hot snapshot) beyond the default limit must be allowed
     // once: up to what fits beside the static LDS in the 160 KiB of a CU.
     const int cap = lds_dynamic_cap<BLOCK>();
     static const bool lds_ok = hipFuncSetAttribute(reinterpret_cast<const void*>(k_expand<OffT, BLOCK, kAtomic>),
                                                    hipFuncAttributeMaxDynamicSharedMemorySize, cap) == hipSuccess;
     if (!lds_ok) fail(BFS_E_DEVICE, "cannot enable dynamic LDS for the expansion kernel");
-    if (hot_words * 4 > cap) fail(BFS_E_INVALID_ARG, "hot bitmap does not fit in LDS beside this workgroup size");
-    const int occ = occupancy_of(k_expand<OffT, BLOCK, kAtomic>, BLOCK, (size_t)hot_words * 4);
+    if (lds_words * 4 > cap) fail(BFS_E_INVALID_ARG, "LDS bitmap does not fit beside this workgroup size");
+    const int occ = occupancy_of(k_expand<OffT, BLOCK, kAtomic>, BLOCK, (size_t)lds_words * 4);
     // On gfx950 one workgroup per CU fewer than the occupancy query reports is
     // resident at once (measured: with the reported count, one workgroup per CU
     // starts only when another finishes); a grid that fits keeps every
@@ -1143,7 +1182,8 @@ Grids grids_for(bfs_graph* g, const bfs_tunables& t, int64_t nslots, int hot_wor
 
 template <typename OffT, int BLOCK, bool kAtomic>
 void launch_typed(bfs_graph* g, const bfs_tunables& t, Workspace* w, SingleParams& p, hipStream_t s) {
-    const Grids gr = grids_for<OffT, BLOCK, kAtomic>(g, t, w->nslots, p.hot_words);
+    const int lds_words = std::max<int>(p.hot_words, p.full_words);
+    const Grids gr = grids_for<OffT, BLOCK, kAtomic>(g, t, w->nslots, lds_words);
     const int init_grid = (int)std::min<int64_t>(std::max<int64_t>(p.n / 4, p.words) / BLOCK + 1, 4096);
     k_init<OffT, BLOCK><<<init_grid, BLOCK, 0, s>>>(p, (int)w->nslots);
     BFS_HIP(hipGetLastError());
@@ -1152,7 +1192,7 @@ void launch_typed(bfs_graph* g, const bfs_tunables& t, Workspace* w, SingleParam
     int chunk = 8;
     while (true) {
         for (int i = 0; i < chunk; ++i) {
-            k_expand<OffT, BLOCK, kAtomic><<<gr.expand, BLOCK, (size_t)p.hot_words * 4, s>>>(p, lvl + i);
+            k_expand<OffT, BLOCK, kAtomic><<<gr.expand, BLOCK, (size_t)lds_words * 4, s>>>(p, lvl + i);
             k_restore<OffT, kAtomic><<<gr.restore, kRestoreBlock, 0, s>>>(p, lvl + i);
         }
         BFS_HIP(hipGetLastError());
@@ -1170,6 +1210,12 @@ void launch_typed(bfs_graph* g, const bfs_tunables& t, Workspace* w, SingleParam
 }
 
 }  // namespace
+
+int64_t lds_visited_words_max(int block) {
+    const int cap = block == 1024 ? lds_dynamic_cap<1024>() : block == 512 ? lds_dynamic_cap<512>()
+                                                                           : lds_dynamic_cap<256>();
+    return cap / 4 / 64 * 64;
+}
 
 void launch_single(bfs_graph* g, const bfs_tunables& t, Workspace* w, int32_t root, int32_t* levels,
                    int32_t* parents, hipStream_t s, bool hybrid) {
@@ -1216,6 +1262,8 @@ void launch_single(bfs_graph* g, const bfs_tunables& t, Workspace* w, int32_t ro
     p.hot_vis = w->hot_vis;
     p.hot_fr = w->hot_fr;
     p.hot_min_frontier = std::max<int64_t>(4096, g->n / 256);
+    p.full_words = (int32_t)lds_visited_words(g, t);
+    if (p.full_words % 64 != 0 || p.full_words > w->words) fail(BFS_E_INTERNAL, "LDS visited words out of range");
     if ((int64_t)p.hot_words * 32 > w->words || p.hot_words % 2 != 0 || p.hot_words > w->hot_capacity)
         fail(BFS_E_INTERNAL, "hot bitmap larger than its buffer");
     if (w->big_capacity < bt.num_big) fail(BFS_E_INTERNAL, "big-row list too small");

@@ -102,6 +102,10 @@ def test_device_pointer_graph():
     dict(hot_vertices=2048),                                    # LDS hot bitmap at every large level
     dict(hot_vertices=2048, update_mode=2),
     dict(hot_vertices=65536, block_size=1024, small_max_degree=256),
+    dict(lds_visited=1, block_size=1024),                       # whole visited bitmap in LDS
+    dict(lds_visited=1, block_size=256, small_max_degree=8, wave_max_degree=32),
+    dict(lds_visited=1, block_size=512, update_mode=2),
+    dict(lds_visited=-1, block_size=1024),
 ])
 def test_bins_and_launch_shapes(tun):
     """Correctness does not depend on the degree bins or the launch shape."""
@@ -193,7 +197,8 @@ def test_rmat_scale20_64_roots():
         check_root(g, dg, int(r))
 
 
-@pytest.mark.parametrize("tun", [dict(hot_vertices=8192, block_size=1024), dict(hot_vertices=8192, update_mode=2)])
+@pytest.mark.parametrize("tun", [dict(hot_vertices=8192, block_size=1024), dict(hot_vertices=8192, update_mode=2),
+                                 dict(lds_visited=1, block_size=1024), dict(lds_visited=-1)])
 def test_hot_bitmap_scale18(tun):
     """The LDS copy of the hot bitmap changes probes only, never results: levels
     exact and parents valid with the hot set on, for several roots."""
@@ -202,3 +207,20 @@ def test_hot_bitmap_scale18(tun):
     bfs.bfs_graph_set_tunables(dg, **tun)
     for r in graphgen.pick_roots(g, 4, seed=12):
         check_root(g, dg, int(r))
+
+
+def test_lds_visited_defaults_and_limit():
+    """The whole visited bitmap goes to LDS by default from 2^16 to 2^20
+    vertices (with 1024-thread workgroups); asking for it where the bitmap
+    cannot fit is an argument error."""
+    small = load(graphgen.rmat(15, 8, seed=31))
+    assert bfs.bfs_graph_get_tunables(small)["lds_visited"] == -1
+    mid = load(graphgen.rmat(17, 8, seed=32))
+    t = bfs.bfs_graph_get_tunables(mid)
+    assert (t["lds_visited"], t["block_size"]) == (1, 1024)
+    t = bfs.bfs_graph_set_tunables(mid, block_size=256)
+    assert t["lds_visited"] == -1  # the default follows the workgroup size
+    big = load(graphgen.path((1 << 21) + 1))
+    with pytest.raises(bfs.BfsError) as e:
+        bfs.bfs_graph_set_tunables(big, lds_visited=1, block_size=1024)
+    assert e.value.status == bfs.BFS_E_INVALID_ARG

@@ -161,7 +161,8 @@ def main() -> int:
                     f"off{off_bytes * 8} tunables{args.tunables or '{}'}{' tuned' if args.tune else ''}"
                     f"{' hybrid' if args.hybrid else ''}")
     traffic = profsum.stored_traffic(
-        os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", f"bfs_run_rmat{args.scale}_hbm_traffic.md"),
+        os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                     f"bfs_run_rmat{args.scale}{'_hybrid' if args.hybrid else ''}_hbm_traffic.md"),
         workload_key)
 
     cpu = None
@@ -208,7 +209,7 @@ def main() -> int:
                    "tunables": bfs.bfs_graph_get_tunables(dg)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "bfs_run: k_init, then k_expand + k_restore per level",
+                     "kernel": "bfs_run: k_init, k_expand + k_restore per level, k_out on the degree-ordered copy",
                      "avg_launch_ms": round(avg_ms, 4), "bytes_alg_per_launch": int(bytes_total / launches),
                      "workload_key": workload_key,
                      **({"note": "bytes follow the top-down definition; bottom-up levels read fewer columns"}

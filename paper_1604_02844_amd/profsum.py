@@ -9,8 +9,9 @@
         --pmc WRITE_SIZE), each scaled by what the same counter reads for the
         plain copy kernel of B bytes in the same process.
 
-The digest of the library sources is written into every summary; bench.py
-reports a stored traffic figure only while the sources still match it.
+The digest of the sources of the single-root kernels is written into every
+summary; bench.py reports a stored traffic figure only while those sources
+still match it.
 """
 from __future__ import annotations
 
@@ -25,19 +26,21 @@ import sys
 from collections import defaultdict
 
 CSRC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
-# Kernels inside the span that bfs_run times (init, then expand/restore per level).
-RUN_KERNELS = ("k_init", "k_expand", "k_restore")
+# Kernels inside the span that bfs_run times (init, expand/restore per level,
+# and on the degree-ordered copy the pass that writes the caller's arrays).
+RUN_KERNELS = ("k_init", "k_expand", "k_restore", "k_out")
+# Sources that define those kernels and the data they touch.
+RUN_SOURCES = ("single.hip", "bfs_internal.h", "graph.cpp")
 COPY_KERNEL_HINT = "_add<"  # torch.add(src, 1, out=dst): reads and writes every byte once
 
 
 def source_digest() -> str:
-    """sha256 over the library's HIP/C++ sources (sorted by name)."""
+    """sha256 over the sources of the single-root run's kernels (RUN_SOURCES)."""
     h = hashlib.sha256()
-    for path in sorted(glob.glob(os.path.join(CSRC, "*"))):
-        if path.endswith((".hip", ".cpp", ".h")):
-            h.update(os.path.basename(path).encode())
-            with open(path, "rb") as f:
-                h.update(f.read())
+    for name in sorted(RUN_SOURCES):
+        h.update(name.encode())
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 

@@ -51,6 +51,8 @@ def load_library(path: str):
     lib.oracle_validate.argtypes = [i64, vp, vp, i64, vp, vp, vp, ctypes.c_int, vp]
     lib.oracle_certify.restype = ctypes.c_int
     lib.oracle_certify.argtypes = [i64, vp, vp, i64, vp, vp, ctypes.c_int, vp]
+    lib.oracle_min_parents.restype = ctypes.c_int
+    lib.oracle_min_parents.argtypes = [i64, vp, vp, i64, vp, vp, vp]
     return lib
 
 
@@ -122,6 +124,25 @@ def certify(offsets, cols, root: int, levels, parents, rows_sorted: bool = True,
     if rc < 0:
         raise ValueError(f"oracle_certify argument error ({rc})")
     return rc, int(bad[0])
+
+
+def min_parents(offsets, cols, root: int, levels, lib=None):
+    """Deterministic predecessors from a level array: the least in-neighbour one
+    level up of every reached non-root vertex (root: itself; unreached: -1)."""
+    lib = lib or _load()
+    off = _as64(offsets)
+    col = _as32(cols)
+    n = len(off) - 1
+    lv = _as32(levels)
+    if len(lv) != n:
+        raise ValueError("length mismatch")
+    pa = np.empty(n, dtype=np.int32)
+    bad = np.full(1, -1, dtype=np.int64)
+    rc = lib.oracle_min_parents(n, off.ctypes.data, col.ctypes.data, int(root), lv.ctypes.data, pa.ctypes.data,
+                                bad.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"oracle_min_parents failed ({rc}, vertex {int(bad[0])})")
+    return pa
 
 
 def bfs_many(offsets, cols, roots, threads: int | None = None):

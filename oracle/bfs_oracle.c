@@ -40,6 +40,14 @@
  *                    shortest path bounds it from above, so V2-V5 hold exactly
  *                    when levels[] is the hop distance and parents[] a BFS tree.
  *
+ *   oracle_min_parents  Deterministic predecessors. Any reached neighbour one
+ *                    layer up is a correct predecessor (section 3.2), so the
+ *                    smallest one is a unique choice: for every reached v other
+ *                    than the root, the least u with an arc u -> v and
+ *                    levels[u] = levels[v] - 1. Written as that definition, one
+ *                    pass over every arc taking minima; it needs only levels[]
+ *                    (any correct level array, e.g. oracle_bfs's).
+ *
  * Pins: tests/test_oracle_*.py check this file against brute force on every
  * labelled graph with n <= 6, unit-weight Bellman-Ford on random digraphs,
  * closed forms (path, cycle, star, complete graph, grid, binary tree, disjoint
@@ -48,7 +56,7 @@
 #include <stdint.h>
 #include <stdlib.h>
 
-enum { ORACLE_OK = 0, ORACLE_E_ARG = -1, ORACLE_E_ROOT = -3, ORACLE_E_MEM = -4 };
+enum { ORACLE_OK = 0, ORACLE_E_ARG = -1, ORACLE_E_ROOT = -3, ORACLE_E_MEM = -4, ORACLE_E_LEVELS = -5 };
 
 /*
  * stats (nullable) receives: [0] R reached vertices, [1] A arcs scanned
@@ -186,4 +194,34 @@ int oracle_certify(int64_t n, const int64_t* offsets, const int32_t* cols, int64
         }
     }
     return 0;
+}
+
+/*
+ * parents[v] = the least in-neighbour of v one level up, for every reached v
+ * other than the root; parents[root] = root; -1 where levels[v] = -1.
+ * Returns ORACLE_E_LEVELS (and *bad_vertex) if a reached vertex other than the
+ * root has no such in-neighbour, i.e. levels[] is not a BFS level array.
+ */
+int oracle_min_parents(int64_t n, const int64_t* offsets, const int32_t* cols, int64_t root,
+                       const int32_t* levels, int32_t* parents, int64_t* bad_vertex) {
+    if (n < 1 || !offsets || !levels || !parents) return ORACLE_E_ARG;
+    if (root < 0 || root >= n) return ORACLE_E_ROOT;
+    if (bad_vertex) *bad_vertex = -1;
+    for (int64_t v = 0; v < n; ++v) parents[v] = levels[v] < 0 ? -1 : INT32_MAX;
+    parents[root] = (int32_t)root;
+    for (int64_t u = 0; u < n; ++u) {
+        if (levels[u] < 0) continue;
+        for (int64_t j = offsets[u]; j < offsets[u + 1]; ++j) {
+            const int32_t v = cols[j];
+            if (levels[v] != levels[u] + 1) continue;  /* the root (level 0) never qualifies */
+            if (u < parents[v]) parents[v] = (int32_t)u;
+        }
+    }
+    for (int64_t v = 0; v < n; ++v) {
+        if (parents[v] == INT32_MAX) {
+            if (bad_vertex) *bad_vertex = v;
+            return ORACLE_E_LEVELS;
+        }
+    }
+    return ORACLE_OK;
 }

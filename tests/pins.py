@@ -233,3 +233,119 @@ def pin_random_digraphs(lib, count: int = 60, seed: int = 11) -> list[str]:
         dst = rng.integers(0, n, m)
         fails += pin_bellman_ford(lib, n, src.tolist(), dst.tolist(), int(rng.integers(0, n)))
     return fails
+
+
+# ---------------------------------------------------------------------------
+# Deterministic predecessors (least in-neighbour one level up)
+# ---------------------------------------------------------------------------
+
+def _min_parent_reference(n, src, dst, dist, root) -> np.ndarray:
+    """From reference distances: least u over arcs u -> v with dist[u] = dist[v] - 1."""
+    ref = np.where(dist >= 0, np.iinfo(np.int32).max, -1).astype(np.int64)
+    for u, v in zip(src, dst):
+        if v != root and dist[u] >= 0 and dist[v] == dist[u] + 1:
+            ref[v] = min(ref[v], u)
+    ref[root] = root
+    return ref
+
+
+def min_parent_closed_forms():
+    """(graph, root, expected least parents) from the shape of the graph alone."""
+    cases = []
+    n = 1000
+    v = np.arange(n)
+    for r in (0, 377, n - 1):
+        exp = np.where(v < r, v + 1, v - 1)
+        exp[r] = r
+        cases.append((graphgen.path(n), r, exp))
+    # Cycle: the vertex opposite the root (even length) has two parents, the
+    # neighbours on either side; the least is the smaller id.
+    for cn, r in ((1000, 0), (1000, 17), (999, 17)):
+        u = np.arange(cn)
+        d = (u - r) % cn
+        fwd = np.where(d <= cn // 2, (u - 1) % cn, (u + 1) % cn)  # one step back along the shorter way
+        exp = fwd.copy()
+        if cn % 2 == 0:
+            opp = (r + cn // 2) % cn
+            exp[opp] = min((opp - 1) % cn, (opp + 1) % cn)
+        exp[r] = r
+        cases.append((graphgen.cycle(cn), r, exp))
+    cases.append((graphgen.complete(60), 11, np.full(60, 11)))
+    exp = np.zeros(500, dtype=np.int64)  # star centre 0: every leaf hangs off it ...
+    exp[0] = exp[7] = 7                     # ... except leaf 7, the root, which is the centre's parent
+    cases.append((graphgen.star(500), 7, exp))
+    # Grid: the neighbours one step closer to the root are (i -/+ 1, j) and
+    # (i, j -/+ 1) toward it; ids are i * C + j, so the row step is the smaller
+    # id exactly when it moves up a row.
+    R, C = 37, 53
+    ri, cj = 20, 9
+    rr, cc = np.divmod(np.arange(R * C), C)
+    cand = np.full(R * C, np.iinfo(np.int64).max)
+    up = rr > ri
+    down = rr < ri
+    left = cc > cj
+    right = cc < cj
+    cand = np.where(up, np.minimum(cand, (rr - 1) * C + cc), cand)
+    cand = np.where(down, np.minimum(cand, (rr + 1) * C + cc), cand)
+    cand = np.where(left, np.minimum(cand, rr * C + cc - 1), cand)
+    cand = np.where(right, np.minimum(cand, rr * C + cc + 1), cand)
+    cand[ri * C + cj] = ri * C + cj
+    cases.append((graphgen.grid(R, C), ri * C + cj, cand))
+    nb = 4095
+    par = (np.arange(nb) - 1) // 2
+    par[0] = 0
+    cases.append((graphgen.binary_tree(nb), 0, par))
+    return cases
+
+
+def pin_min_parents(lib) -> list[str]:
+    fails = []
+    for g, r, exp in min_parent_closed_forms():
+        lv, _, _ = oracle.bfs(g.offsets, g.cols, r, lib=lib)
+        try:
+            pa = oracle.min_parents(g.offsets, g.cols, r, lv, lib=lib)
+        except ValueError as e:
+            fails.append(f"{g.name} root {r}: {e}")
+            continue
+        if not np.array_equal(pa, exp):
+            bad = np.nonzero(pa != exp)[0][:5]
+            fails.append(f"{g.name} root {r}: least parents differ at {bad.tolist()}")
+    # Every labelled simple graph on 4 vertices, every root, against matrix-power distances.
+    n = 4
+    adj = all_graph_adjacency(n)
+    dist = matrix_power_levels(adj)
+    for gi in range(adj.shape[0]):
+        src, dst = np.nonzero(adj[gi])
+        offsets = np.zeros(n + 1, dtype=np.int64)
+        np.cumsum(np.bincount(src, minlength=n), out=offsets[1:])
+        for r in range(n):
+            ref = _min_parent_reference(n, src.tolist(), dst.tolist(), dist[gi, r], r)
+            try:
+                pa = oracle.min_parents(offsets, dst.astype(np.int32), r, dist[gi, r], lib=lib)
+            except ValueError as e:
+                fails.append(f"exhaustive n=4 graph {gi} root {r}: {e}")
+                continue
+            if not np.array_equal(pa, ref):
+                fails.append(f"exhaustive n=4 graph {gi} root {r}: {pa.tolist()} != {ref.tolist()}")
+            if len(fails) > 5:
+                return fails
+    # Random digraphs with self-loops and duplicates, against Bellman-Ford distances.
+    rng = np.random.default_rng(19)
+    for _ in range(20):
+        n = int(rng.integers(1, 40))
+        m = int(rng.integers(0, 4 * n))
+        src = rng.integers(0, n, m).tolist()
+        dst = rng.integers(0, n, m).tolist()
+        r = int(rng.integers(0, n))
+        g = graphgen.from_edges(n, src, dst, symmetric=False, dedupe=False, drop_self_loops=False,
+                                sort_rows=False)
+        dist = bellman_ford_levels(n, src, dst, r)
+        ref = _min_parent_reference(n, src, dst, dist, r)
+        try:
+            pa = oracle.min_parents(g.offsets, g.cols, r, dist, lib=lib)
+        except ValueError as e:
+            fails.append(f"digraph n={n} root {r}: {e}")
+            continue
+        if not np.array_equal(pa, ref):
+            fails.append(f"digraph n={n} root {r}: least parents differ")
+    return fails

@@ -13,7 +13,8 @@ from tests import pins
 def main(path: str) -> int:
     lib = oracle.load_library(path)
     for pin in (lambda: pins.pin_paper_examples(lib), lambda: pins.pin_closed_forms(lib),
-                lambda: pins.pin_exhaustive(lib, 4), lambda: pins.pin_random_digraphs(lib, 20)):
+                lambda: pins.pin_exhaustive(lib, 4), lambda: pins.pin_random_digraphs(lib, 20),
+                lambda: pins.pin_min_parents(lib)):
         fails = pin()
         if fails:
             print("PIN FAILED:", fails[0])

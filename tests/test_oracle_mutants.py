@@ -35,6 +35,14 @@ MUTANTS = {
     "row_end_wrong": ("end = offsets[u + 1];", "end = offsets[u] + 1;"),
     "operand_transposed": ("int32_t v = cols[j];", "int32_t v = (int32_t)(j % n);"),
     "init_zero": ("levels[v] = -1;\n        parents[v] = -1;", "levels[v] = 0;\n        parents[v] = -1;"),
+    "min_parent_takes_max": ("if (u < parents[v]) parents[v] = (int32_t)u;",
+                             "if (parents[v] == INT32_MAX || u > parents[v]) parents[v] = (int32_t)u;"),
+    "min_parent_same_level": ("if (levels[v] != levels[u] + 1) continue;  /* the root",
+                              "if (levels[v] != levels[u]) continue;  /* the root"),
+    "min_parent_root_not_seeded": ("parents[root] = (int32_t)root;\n    for (int64_t u = 0; u < n; ++u) {\n        if (levels[u] < 0)",
+                                   "for (int64_t u = 0; u < n; ++u) {\n        if (levels[u] < 0)"),
+    "min_parent_last_arc_dropped": ("for (int64_t j = offsets[u]; j < offsets[u + 1]; ++j) {\n            const int32_t v = cols[j];\n            if (levels[v] != levels[u] + 1)",
+                                    "for (int64_t j = offsets[u]; j + 1 < offsets[u + 1]; ++j) {\n            const int32_t v = cols[j];\n            if (levels[v] != levels[u] + 1)"),
 }
 
 

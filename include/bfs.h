@@ -74,6 +74,11 @@ extern "C" {
                                        bottom-up (every unvisited vertex looks for a frontier
                                        neighbour) instead of top-down; same levels, valid
                                        parents. Requires a graph loaded with BFS_LOAD_SYMMETRIC. */
+#define BFS_DETERMINISTIC 0x10u     /* bfs_run only: after the levels are final, every reached
+                                       vertex other than the root gets the least in-neighbour one
+                                       level up as parent (any such neighbour is correct, section
+                                       3.2; the least is unique), so parents[] no longer depends on
+                                       the timing of the run. Part of the timed run. */
 
 typedef struct bfs_graph bfs_graph;
 typedef struct bfs_server bfs_server;
@@ -162,7 +167,10 @@ int bfs_graph_set_tunables(bfs_graph* g, const bfs_tunables* t);
  *                    the sum of degrees of the reached vertices.
  *   st               nullable; filled on return (must be NULL with BFS_ASYNC).
  * Errors: BFS_E_ROOT_RANGE, BFS_E_INVALID_ARG (also BFS_HYBRID on a graph not loaded
- * with BFS_LOAD_SYMMETRIC), BFS_E_DEVICE, BFS_E_NO_MEMORY.
+ * with BFS_LOAD_SYMMETRIC), BFS_E_DEVICE, BFS_E_NO_MEMORY. BFS_DETERMINISTIC works on
+ * any graph: on a symmetric one each vertex scans its own row (stopping at the first
+ * hit when rows are sorted), otherwise every reached vertex offers itself to its
+ * out-neighbours with atomicMin.
  * Reentrant for distinct streams and outputs on the same graph.
  */
 int bfs_run(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents, void* stream,

@@ -39,6 +39,7 @@ BFS_LOAD_SYMMETRIC = 0x8
 BFS_OUT_HOST = 0x1
 BFS_ASYNC = 0x2
 BFS_HYBRID = 0x4
+BFS_DETERMINISTIC = 0x10
 
 ABI_SYMBOLS = [
     "bfs_graph_load_csr", "bfs_graph_free", "bfs_graph_info", "bfs_graph_get_tunables",
@@ -105,6 +106,13 @@ def load_library():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"libbfs.so not found at {LIB_PATH}; build it with "
                            "`python -m paper_1604_02844_amd.build` (no CPU fallback exists)")
+    # PyTorch ships its own HIP runtime. Import it first, when it is installed,
+    # so that libbfs.so binds to that same runtime: with the system runtime
+    # loaded first, torch later finds no GPU in this process.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, u32, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
     P = ctypes.POINTER

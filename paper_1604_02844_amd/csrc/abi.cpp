@@ -134,8 +134,10 @@ int bfs_run(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents, void*
             bfs_run_stats* st) {
     return guarded([&] {
         if (!g || !levels || !parents) bfs::fail(BFS_E_INVALID_ARG, "NULL argument");
-        if (flags & ~(BFS_OUT_HOST | BFS_ASYNC | BFS_HYBRID)) bfs::fail(BFS_E_INVALID_ARG, "unknown run flag");
+        if (flags & ~(BFS_OUT_HOST | BFS_ASYNC | BFS_HYBRID | BFS_DETERMINISTIC))
+            bfs::fail(BFS_E_INVALID_ARG, "unknown run flag");
         const bool host_out = flags & BFS_OUT_HOST, async = flags & BFS_ASYNC, hybrid = flags & BFS_HYBRID;
+        const bool least_parents = flags & BFS_DETERMINISTIC;
         if (async && (host_out || st)) bfs::fail(BFS_E_INVALID_ARG, "BFS_ASYNC excludes BFS_OUT_HOST and stats");
         if (root < 0 || root >= g->n) bfs::fail(BFS_E_ROOT_RANGE, "root out of range");
         if (hybrid && !g->symmetric) bfs::fail(BFS_E_INVALID_ARG, "BFS_HYBRID needs a graph loaded with BFS_LOAD_SYMMETRIC");
@@ -153,6 +155,7 @@ int bfs_run(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents, void*
             }
             BFS_HIP(hipEventRecord(w->ev_start, s));
             bfs::launch_single(g, t, w, root, lv, pa, s, hybrid);
+            if (least_parents) bfs::launch_least_parents(g, lv, pa, s);
             BFS_HIP(hipEventRecord(w->ev_stop, s));
             if (host_out) {
                 BFS_HIP(hipMemcpyAsync(levels, lv, (size_t)g->n * 4, hipMemcpyDeviceToHost, s));

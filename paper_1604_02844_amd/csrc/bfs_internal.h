@@ -154,6 +154,7 @@ struct bfs_graph {
     bool off32 = false;        // 4-byte offsets on the device
     bool owns = true;          // device arrays allocated by the library
     bool symmetric = false;    // loaded with BFS_LOAD_SYMMETRIC (checked unless validation is skipped)
+    bool rows_sorted = false;  // symmetric graphs: every row lists ids in non-decreasing order
     void* d_off = nullptr;     // int64_t[n+1] or int32_t[n+1]
     int32_t* d_col = nullptr;  // int32_t[nnz]
     int64_t max_degree = 0;
@@ -225,6 +226,10 @@ void launch_single_stats_from_levels(bfs_graph* g, const bfs_tunables& t, Worksp
                                      hipStream_t s);
 // Symmetry check of a resident CSR (a multiset hash of arcs against reversed arcs).
 bool csr_is_symmetric(const bfs_graph* g);
+bool csr_rows_sorted(const bfs_graph* g);
+// Deterministic predecessors (BFS_DETERMINISTIC): after a run, parents[v] = the
+// least in-neighbour one level up, on the caller's ids (parents.hip).
+void launch_least_parents(const bfs_graph* g, const int32_t* levels, int32_t* parents, hipStream_t s);
 void launch_fill_i32(int32_t* p, int64_t count, int32_t value, hipStream_t s);
 
 // Multi-source engine (multi.hip). A batch runs every level device-side with

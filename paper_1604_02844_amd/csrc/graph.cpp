@@ -521,6 +521,7 @@ bfs_graph* load_csr(int64_t n, int64_t nnz, const void* offsets, const int32_t* 
             if (!(flags & BFS_LOAD_SKIP_VALIDATE) && !csr_is_symmetric(g))
                 fail(BFS_E_INVALID_GRAPH, "BFS_LOAD_SYMMETRIC: the arcs and the reversed arcs differ");
             g->symmetric = true;
+            g->rows_sorted = csr_rows_sorted(g);
         }
         g->restore_grid = restore_grid_for(padded_words(n), g->cu_count);
         build_big_table(g->big, g->d_off, g->off32, n, default_tunables(nullptr).wave_max_degree, g->restore_grid,

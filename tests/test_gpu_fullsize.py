@@ -49,6 +49,21 @@ def test_hybrid_rmat24():
         assert st["reached"] == int((lv >= 0).sum())
 
 
+def test_least_parents_rmat24():
+    """Deterministic parents at full size, top-down and direction-optimising."""
+    torch_mod()
+    g = graphgen.cached("rmat", scale=24, edgefactor=16, seed=1)
+    dg = load(g, symmetric=True)
+    r = int(graphgen.pick_roots(g, 64, seed=2)[0])
+    ref, _, _ = oracle.bfs(g.offsets, g.cols, r)
+    exp = oracle.min_parents(g.offsets, g.cols, r, ref)
+    for flags in (bfs.BFS_DETERMINISTIC, bfs.BFS_DETERMINISTIC | bfs.BFS_HYBRID):
+        print(f"[case] least parents scale 24 root {r} flags {flags}", flush=True)
+        lv, pa, _ = gpu_run(dg, r, flags=flags)
+        assert np.array_equal(lv, ref)
+        assert np.array_equal(pa, exp)
+
+
 def test_batch_rmat22_64_roots():
     torch = torch_mod()
     g = graphgen.cached("rmat", scale=22, edgefactor=16, seed=1)

@@ -56,6 +56,7 @@ struct Workspace {
     uint32_t* vis_prev = nullptr;   // exact visited bits at the start of the level
     uint32_t* fr = nullptr;         // exact frontier bits of the current level
     Ctrl* ctrl = nullptr;
+    int last_launches = 0;          // level launches the previous single-root run needed
     unsigned long long* slots = nullptr;  // per-block partial sums (arcs | reached)
     int64_t nslots = 0;
     // Frontier rows above T2, compacted by the restore pass into one segment per

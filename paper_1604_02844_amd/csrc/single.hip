@@ -893,6 +893,9 @@ __global__ __launch_bounds__(kRestoreBlock) void k_restore(SingleParams p, int l
     unsigned long long found = 0;
     uint32_t seg_n = 0, seg_a = 0;  // running totals of this block's segment
     const int32_t first = p.seg_start[bid];
+    // A bottom-up level wrote every changed word once, from its owner, with
+    // exactly the new bits: no lost updates to put back.
+    const bool exact_words = kAtomic || (p.hybrid && ld(&p.ctrl->dir[(lvl + 1) & 1]) != 0);
     for (int64_t c = bid; c * BLOCK < p.words; c += G) {
         const int64_t w = c * BLOCK + tid;
         const int lane = tid & 63;
@@ -902,7 +905,7 @@ __global__ __launch_bounds__(kRestoreBlock) void k_restore(SingleParams p, int l
             prev = ld(p.vis_prev + w);
         }
         const bool touched = w < p.words && cur != prev;
-        if (kAtomic) {
+        if (exact_words) {
             exact = touched ? (cur & ~prev) : 0u;
         } else {
             // A racing read-modify-write may have dropped bits (of this level,
@@ -1187,9 +1190,12 @@ void launch_typed(bfs_graph* g, const bfs_tunables& t, Workspace* w, SingleParam
     const int init_grid = (int)std::min<int64_t>(std::max<int64_t>(p.n / 4, p.words) / BLOCK + 1, 4096);
     k_init<OffT, BLOCK><<<init_grid, BLOCK, 0, s>>>(p, (int)w->nslots);
     BFS_HIP(hipGetLastError());
-    // Levels are enqueued in chunks; between chunks the host reads the done flag.
+    // Levels are enqueued in chunks; between chunks the host reads the done
+    // flag. The first chunk covers as many levels as the previous run on this
+    // workspace needed (runs from other roots of one graph have similar depth),
+    // so most runs end inside it with few idle launches and one wait.
     int lvl = 0;
-    int chunk = 8;
+    int chunk = std::max(8, std::min(64, w->last_launches + 1));
     while (true) {
         for (int i = 0; i < chunk; ++i) {
             k_expand<OffT, BLOCK, kAtomic><<<gr.expand, BLOCK, (size_t)lds_words * 4, s>>>(p, lvl + i);
@@ -1197,11 +1203,14 @@ void launch_typed(bfs_graph* g, const bfs_tunables& t, Workspace* w, SingleParam
         }
         BFS_HIP(hipGetLastError());
         lvl += chunk;
-        BFS_HIP(hipMemcpyAsync(&w->host_ctrl->done, &p.ctrl->done, sizeof(int), hipMemcpyDeviceToHost, s));
+        static_assert(offsetof(Ctrl, num_levels) == offsetof(Ctrl, done) + sizeof(int), "done, then num_levels");
+        BFS_HIP(hipMemcpyAsync(&w->host_ctrl->done, &p.ctrl->done, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
         BFS_HIP(hipStreamSynchronize(s));
         if (w->host_ctrl->done || lvl > p.n + 1) break;
         chunk = chunk < 64 ? chunk * 2 : 64;
     }
+    // The level that found the frontier empty was the last launch with work.
+    if (w->host_ctrl->done) w->last_launches = w->host_ctrl->num_levels + 1;
     if (p.new2old) {
         const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((p.n + 255) / 256, (int64_t)g->cu_count * 16));
         k_out<<<blocks, 256, 0, s>>>(reinterpret_cast<const int2*>(p.lv), p.new2old, p.out_lv, p.out_pa, p.n);

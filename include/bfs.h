@@ -119,6 +119,12 @@ typedef struct {
                                    does not fit in LDS beside the workgroup), -1 = off, 0 =
                                    library default (on for 2^16..2^20 vertices, with 1024-thread
                                    workgroups) */
+    int32_t sparse_frontier;    /* single-root runs: a level whose frontier has at most this
+                                   many vertices (at most 4096) and at most 4 times as many arcs
+                                   is expanded by one workgroup from a list of the frontier, with
+                                   exact atomicOr claims, and consecutive such levels run in one
+                                   launch; costs one more launch per level; -1 = off, 0 = library
+                                   default (off) */
 } bfs_tunables;
 
 /* ---- graph residency ------------------------------------------------------ */

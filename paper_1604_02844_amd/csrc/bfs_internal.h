@@ -41,11 +41,18 @@ struct Ctrl {
     int done;                      // set by the first level that finds an empty frontier
     int num_levels;
     int status;
-    int pad;
+    int steps;                     // single-root: steps (small-level kernel, expand, restore) that ran
     // Direction-optimising runs, indexed by level parity: the direction chosen
     // for the level (1 = bottom-up) and the vertices visited before its frontier.
     int dir[2];
     unsigned long long visited[2];
+    // Single-root level control: the level the next expand/restore pair works
+    // on, whether the small-level kernel already expanded it (the expand then
+    // skips it), and whether a restore ran since the small-level kernel last looked.
+    int level;
+    int skip_e;
+    int r_ran;
+    int pad2;
 };
 
 // Scratch of one single-root run.
@@ -56,7 +63,11 @@ struct Workspace {
     uint32_t* vis_prev = nullptr;   // exact visited bits at the start of the level
     uint32_t* fr = nullptr;         // exact frontier bits of the current level
     Ctrl* ctrl = nullptr;
-    int last_launches = 0;          // level launches the previous single-root run needed
+    int last_launches = 0;          // level steps the previous single-root run needed
+    // Next frontier of each restore block, listed when it is small: up to
+    // kSmallSeg ids per block, and the block's count (above kSmallSeg: not all listed).
+    int32_t* sl = nullptr;
+    int32_t* sl_cnt = nullptr;
     unsigned long long* slots = nullptr;  // per-block partial sums (arcs | reached)
     int64_t nslots = 0;
     // Frontier rows above T2, compacted by the restore pass into one segment per
@@ -209,6 +220,8 @@ constexpr int kRestoreBlock = 256;
 constexpr int kMaxRestoreGrid = 1024;
 // Largest LDS snapshot of hot visited words per expansion workgroup (128 KiB).
 constexpr int kMaxHotWords = 32768;
+constexpr int kSmallSeg = 64;      // listed next-frontier ids per restore block
+constexpr int kSmallMax = 4096;    // largest frontier the single-workgroup level kernel takes
 int restore_grid_for(int64_t words, int cu_count);
 
 Workspace* acquire_ws(bfs_graph* g, hipStream_t s);

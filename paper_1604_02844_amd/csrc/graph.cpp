@@ -303,6 +303,7 @@ bfs_tunables default_tunables(const bfs_graph* g) {
     const bool fits = g && !large && g->n >= (int64_t)1 << 16 &&
                       padded_words(g->n) <= lds_visited_words_max(1024);
     t.lds_visited = fits ? 1 : -1;
+    t.sparse_frontier = -1;  // measured slower at R-MAT scale 20 and 24 (see the design notes)
     if (fits) t.block_size = 1024;
     return t;
 }
@@ -323,6 +324,9 @@ bfs_tunables resolve_tunables(const bfs_graph* g, const bfs_tunables& in) {
     // workgroups only: with fewer waves per copy it costs occupancy.
     if (t.lds_visited == 0) t.lds_visited = d.lds_visited > 0 && t.block_size == 1024 ? 1 : -1;
     t.lds_visited = t.lds_visited > 0 ? 1 : -1;
+    if (t.sparse_frontier == 0) t.sparse_frontier = d.sparse_frontier;
+    if (t.sparse_frontier < 0) t.sparse_frontier = -1;
+    if (t.sparse_frontier > kSmallMax) t.sparse_frontier = kSmallMax;
     if (t.hot_vertices == 0) t.hot_vertices = d.hot_vertices;
     if (t.hot_vertices < 0) t.hot_vertices = -1;
     if (t.hot_vertices > kMaxHotWords * 32) t.hot_vertices = kMaxHotWords * 32;
@@ -358,7 +362,8 @@ Workspace* acquire_ws(bfs_graph* g, hipStream_t s) {
         w->hot_capacity = (int)std::min<int64_t>(w->words / 32, kMaxHotWords);
         const size_t hotb = (size_t)w->hot_capacity * 8;  // visited and frontier bits
         const size_t recb = g->hot ? (size_t)g->n * 8 : 0;  // {level, parent} in the degree-ordered ids
-        const size_t pre_rec = bmb * 3 + sizeof(Ctrl) + (size_t)w->nslots * 2 * 8 + listb + hotb;
+        const size_t smallb = (size_t)g->restore_grid * (kSmallSeg + 1) * 4;  // listed small frontiers
+        const size_t pre_rec = bmb * 3 + sizeof(Ctrl) + (size_t)w->nslots * 2 * 8 + listb + hotb + smallb;
         const size_t rec_at = (pre_rec + 255) & ~(size_t)255;
         const size_t total = rec_at + recb;
         char* base = nullptr;
@@ -376,6 +381,8 @@ Workspace* acquire_ws(bfs_graph* g, hipStream_t s) {
         w->hot_vis = reinterpret_cast<uint32_t*>(lp + listb);
         w->hot_fr = w->hot_vis + w->hot_capacity;
         w->run_rec = recb ? reinterpret_cast<int32_t*>(base + rec_at) : nullptr;
+        w->sl = reinterpret_cast<int32_t*>(lp + listb + hotb);
+        w->sl_cnt = w->sl + (size_t)g->restore_grid * kSmallSeg;
         BFS_HIP(hipMemset(w->ctrl, 0, sizeof(Ctrl)));
         BFS_HIP(hipHostMalloc(&w->host_ctrl, sizeof(Ctrl), hipHostMallocDefault));
         BFS_HIP(hipEventCreate(&w->ev_start));

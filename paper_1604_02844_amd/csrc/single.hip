@@ -56,7 +56,8 @@ namespace {
 constexpr int kUnroll = 2;     // arcs per lane in flight: one wavefront per row (T1 < d <= T2)
 constexpr int kLbsUnroll = 4;  // arcs per lane in flight: packed rows (d <= T1)
 constexpr int kBigUnroll = 4;  // arcs per lane in flight: rows above T2
-constexpr int kBuFirst = 4;    // bottom-up: arcs each lane checks before its wavefront helps
+constexpr int kBuFirst = 4;       // bottom-up: arcs each lane checks before its wavefront helps
+constexpr int kSmallBlock = 1024;  // threads of the small-level kernel
 
 struct SingleParams {
     const void* off;
@@ -100,6 +101,13 @@ struct SingleParams {
     int32_t full_words;
     int64_t nnz;
     int32_t hybrid;            // levels with large frontiers may run bottom-up (symmetric graphs)
+    // Small levels: each restore block lists up to kSmallSeg ids of the next
+    // frontier (sl) and counts them (sl_cnt); frontiers of at most s_max
+    // vertices and s_arcs arcs go to the single-workgroup level kernel (s_max 0 = off).
+    int32_t* sl;
+    int32_t* sl_cnt;
+    int32_t s_max;
+    int64_t s_arcs;
 };
 
 
@@ -702,6 +710,15 @@ __global__ __launch_bounds__(BLOCK) void k_init(SingleParams p, int nslots) {
         p.ctrl->dir[1] = 0;
         p.ctrl->visited[0] = 0;
         p.ctrl->visited[1] = 0;
+        p.ctrl->level = 0;
+        p.ctrl->skip_e = 0;
+        p.ctrl->r_ran = 0;
+        p.ctrl->steps = 0;
+    }
+    // The first frontier, listed for the small-level kernel: the root alone.
+    for (int64_t i = gtid; i < p.restore_grid; i += gsize) {
+        p.sl_cnt[i] = i == 0 ? 1 : 0;
+        if (i == 0) p.sl[0] = p.root;
     }
 }
 
@@ -721,12 +738,16 @@ __global__ __launch_bounds__(256) void k_out(const int2* rec, const int32_t* new
 
 // Expansion of level `lvl` (frontier bitmap p.fr).
 template <typename OffT, int BLOCK, bool kAtomic>
-__global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl) {
+__global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl_arg) {
     constexpr int NW = BLOCK / 64;
     __shared__ ExpandShared<BLOCK> sh;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int64_t G = gridDim.x, bid = blockIdx.x;
     if (ld(&p.ctrl->done)) return;
+    // With the small-level kernel on (lvl_arg < 0) the level lives in the
+    // control block, and that kernel may have expanded it already.
+    if (lvl_arg < 0 && ld(&p.ctrl->skip_e)) return;
+    const int lvl = lvl_arg >= 0 ? lvl_arg : ld(&p.ctrl->level);
 
     // Termination: the restore pass of the previous level counted this frontier.
     if (tid < 64) {
@@ -882,12 +903,16 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl) {
 // next frontier bitmap, the discovered count (striped), and the compacted list
 // of the next frontier's rows above T2 (this block's segment).
 template <typename OffT, bool kAtomic>
-__global__ __launch_bounds__(kRestoreBlock) void k_restore(SingleParams p, int lvl) {
+__global__ __launch_bounds__(kRestoreBlock) void k_restore(SingleParams p, int lvl_arg) {
     constexpr int BLOCK = kRestoreBlock;
     __shared__ unsigned long long red[BLOCK / 64];
     __shared__ uint32_t tmp[BLOCK / 64];
+    __shared__ uint32_t listed;  // next-frontier ids of this block so far
     if (ld(&p.ctrl->done)) return;
+    const int lvl = lvl_arg >= 0 ? lvl_arg : ld(&p.ctrl->level);
     const int tid = threadIdx.x;
+    if (tid == 0) listed = 0;
+    __syncthreads();
     const int64_t G = gridDim.x, bid = blockIdx.x;
     const int next = lvl + 1;
     unsigned long long found = 0;
@@ -954,6 +979,13 @@ __global__ __launch_bounds__(kRestoreBlock) void k_restore(SingleParams p, int l
             st(p.fr + w, exact);
             found += (unsigned long long)__popc(exact);
         }
+        // List the block's next-frontier ids while there are few (for the
+        // small-level kernel).
+        if (p.s_max > 0 && exact) {
+            uint32_t at = atomicAdd(&listed, (uint32_t)__popc(exact));
+            for (uint32_t x = exact; x && at < (uint32_t)kSmallSeg; x &= x - 1, ++at)
+                st(p.sl + bid * kSmallSeg + at, (int32_t)(w * 32 + __builtin_ctz(x)));
+        }
         // Append the next frontier's big rows of this chunk to the segment.
         const uint32_t big = w < p.words ? (exact & p.bigmap[w]) : 0u;
         uint32_t my_arcs = 0;
@@ -991,6 +1023,185 @@ __global__ __launch_bounds__(kRestoreBlock) void k_restore(SingleParams p, int l
         st(p.seg_cnt + bid, seg_n);
         st(p.seg_arcs + bid, seg_a);
         if (seg_a) atomicAdd(&p.ctrl->bigarcs[next & 1][(bid % kStripes) * kStripeStride], (unsigned long long)seg_a);
+        if (p.s_max > 0) {
+            st(p.sl_cnt + bid, (int32_t)listed);
+            if (bid == 0) st(&p.ctrl->r_ran, 1);
+        }
+    }
+}
+
+// Small levels (a sparse frontier; tunable sparse_frontier, off by default),
+// one workgroup, launched before every expand/restore pair. It first advances the run's level past a restore that
+// ran, then, while the frontier is a short list (at most s_max vertices and
+// s_arcs arcs), expands it itself: arcs are spread over the threads, claims
+// are exact (atomicOr on the visited word), and the next frontier is listed in
+// LDS. Consecutive small levels run in this one launch. It stops at:
+//  * an empty next frontier: the run is done;
+//  * a large next frontier: the level it just expanded is left for the
+//    following restore, exactly as an expansion would leave it (claims
+//    recorded, visited bits set, the snapshot unchanged), and the following
+//    expansion is told to skip it.
+// A frontier that is large from the start is left to the expansion kernel.
+template <typename OffT>
+__global__ __launch_bounds__(kSmallBlock) void k_small(SingleParams p) {
+    constexpr int B = kSmallBlock;
+    constexpr int PER = kSmallMax / B;  // list entries per thread
+    __shared__ int32_t list[2][kSmallMax];
+    __shared__ int64_t beg[kSmallMax];
+    __shared__ uint32_t pre[kSmallMax];  // exclusive arc prefix of the current list
+    __shared__ uint32_t tmp[B / 64];
+    __shared__ unsigned long long red[B / 64];
+    __shared__ int s_lvl, s_over;
+    __shared__ uint32_t s_next;
+    const int tid = threadIdx.x, lane = tid & 63;
+    if (ld(&p.ctrl->done)) return;
+    if (tid == 0) {
+        int lvl = ld(&p.ctrl->level);
+        if (ld(&p.ctrl->r_ran)) {
+            ++lvl;
+            st(&p.ctrl->level, lvl);
+            st(&p.ctrl->r_ran, 0);
+        }
+        st(&p.ctrl->skip_e, 0);
+        st(&p.ctrl->steps, ld(&p.ctrl->steps) + 1);
+        s_lvl = lvl;
+        s_over = 0;
+        s_next = 0;
+    }
+    __syncthreads();
+    if (p.s_max <= 0) return;
+    int lvl = s_lvl;
+
+    // The frontier from the restore blocks' lists (one block per thread).
+    const int R = p.restore_grid;
+    const int cb = tid < R ? ld(p.sl_cnt + tid) : 0;
+    if (cb > kSmallSeg) s_over = 1;
+    uint32_t excl;
+    uint32_t nf = block_excl_scan<B>((uint32_t)(cb > kSmallSeg ? 0 : cb), excl, tmp);
+    if (s_over || nf == 0 || nf > (uint32_t)p.s_max) return;  // the expansion kernel takes it
+    for (int k = 0; k < cb; ++k) list[0][excl + k] = ld(p.sl + tid * kSmallSeg + k);
+    __syncthreads();
+
+    unsigned long long arcs_done = 0, reached_done = 0;  // this launch's statistics (thread 0)
+    unsigned long long seen = p.hybrid ? ld(&p.ctrl->visited[lvl & 1]) : 0;
+    int cur = 0;
+    bool first = true;
+    while (true) {
+        // Row starts and the exclusive arc prefix of the current list.
+        int64_t d[PER];
+        unsigned long long mine = 0;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int i = tid * PER + k;
+            d[k] = 0;
+            if (i < (int)nf) {
+                const int32_t u = list[cur][i];
+                const int64_t b = load_off<OffT>(p.off, u);
+                beg[i] = b;
+                d[k] = load_off<OffT>(p.off, (int64_t)u + 1) - b;
+            }
+            mine += (unsigned long long)d[k];
+        }
+        if (first) {
+            // Checked in 64 bits: a few hub rows can exceed any 32-bit prefix.
+            unsigned long long tot = wave_sum(mine);
+            if (lane == 0) red[tid >> 6] = tot;
+            __syncthreads();
+            tot = 0;
+            for (int i = 0; i < B / 64; ++i) tot += red[i];
+            __syncthreads();
+            if ((int64_t)tot > p.s_arcs) return;  // too many arcs: the expansion kernel takes it
+            first = false;
+        }
+        // From here the level has at most s_arcs arcs: 32-bit prefixes suffice.
+        uint32_t at;
+        const uint32_t arcs = block_excl_scan<B>((uint32_t)mine, at, tmp);
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int i = tid * PER + k;
+            if (i < (int)nf) pre[i] = at;
+            at += (uint32_t)d[k];
+        }
+        __syncthreads();
+        // Expand: arc a belongs to the last entry whose prefix is at most a.
+        int32_t* nxt = list[cur ^ 1];
+        for (uint32_t a = tid; a < arcs; a += B) {
+            int lo = 0, hi = (int)nf - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (pre[mid] <= a) lo = mid; else hi = mid - 1;
+            }
+            const int32_t u = list[cur][lo];
+            const int32_t v = p.col[beg[lo] + (a - pre[lo])];
+            const uint32_t bit = 1u << (v & 31);
+            uint32_t* wp = p.vis + ((uint32_t)v >> 5);
+            if (!(ld(wp) & bit) && !(atomicOr(wp, bit) & bit)) {
+                record(p, v, lvl + 1, out_id(p, u));
+                const uint32_t k = atomicAdd(&s_next, 1u);
+                if (k < (uint32_t)kSmallMax) nxt[k] = v;
+            }
+        }
+        __syncthreads();
+        const uint32_t nn = s_next;
+        if (tid == 0) arcs_done += arcs;
+        if (p.hybrid && tid == 0) {
+            st(&p.ctrl->dir[(lvl + 1) & 1], 0);
+            st(&p.ctrl->visited[(lvl + 1) & 1], seen + nf);
+        }
+        seen += nf;
+        if (nn == 0) {  // nothing new: level lvl + 1 is empty and the run is done
+            if (tid == 0) {
+                st(p.arcs_slot, ld(p.arcs_slot) + arcs_done);
+                st(p.reached_slot, ld(p.reached_slot) + reached_done);
+                p.ctrl->num_levels = lvl + 1;
+                __hip_atomic_store(&p.ctrl->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            return;
+        }
+        // Is the next frontier small too (vertices, then arcs)?
+        unsigned long long next_arcs = 0;
+        if (nn <= (uint32_t)p.s_max) {
+            for (uint32_t i = tid; i < nn; i += B) {
+                const int32_t v = nxt[i];
+                next_arcs += (unsigned long long)(load_off<OffT>(p.off, (int64_t)v + 1) - load_off<OffT>(p.off, v));
+            }
+            next_arcs = wave_sum(next_arcs);
+            if (lane == 0) red[tid >> 6] = next_arcs;
+            __syncthreads();
+            next_arcs = 0;
+            for (int i = 0; i < B / 64; ++i) next_arcs += red[i];
+        }
+        const bool go_on = nn <= (uint32_t)p.s_max && (int64_t)next_arcs <= p.s_arcs;
+        if (!go_on) {
+            // Leave level lvl to the following restore: its counters start at
+            // zero as an expansion would have set them, and that expansion skips.
+            if (tid < kStripes) {
+                st(stripe(p.ctrl, (lvl + 1) & 1, tid), 0ull);
+                st(&p.ctrl->bigarcs[(lvl + 1) & 1][tid * kStripeStride], 0ull);
+            }
+            if (tid == 0) {
+                st(p.arcs_slot, ld(p.arcs_slot) + arcs_done);
+                st(p.reached_slot, ld(p.reached_slot) + reached_done);
+                st(&p.ctrl->level, lvl);
+                st(&p.ctrl->skip_e, 1);
+            }
+            return;
+        }
+        // The next frontier stays here: the snapshot and the hot bits take it in.
+        for (uint32_t i = tid; i < nn; i += B) {
+            const int32_t v = nxt[i];
+            atomicOr(p.vis_prev + ((uint32_t)v >> 5), 1u << (v & 31));
+            const uint32_t r = (uint32_t)v >> 5;
+            if ((v & 31) == 0 && r < (uint32_t)p.hot_words * 32u) atomicOr(p.hot_vis + (r >> 5), 1u << (r & 31));
+        }
+        if (tid == 0) {
+            reached_done += nn;
+            s_next = 0;
+        }
+        __syncthreads();
+        cur ^= 1;
+        nf = nn;
+        ++lvl;
     }
 }
 
@@ -1190,27 +1401,33 @@ void launch_typed(bfs_graph* g, const bfs_tunables& t, Workspace* w, SingleParam
     const int init_grid = (int)std::min<int64_t>(std::max<int64_t>(p.n / 4, p.words) / BLOCK + 1, 4096);
     k_init<OffT, BLOCK><<<init_grid, BLOCK, 0, s>>>(p, (int)w->nslots);
     BFS_HIP(hipGetLastError());
-    // Levels are enqueued in chunks; between chunks the host reads the done
-    // flag. The first chunk covers as many levels as the previous run on this
-    // workspace needed (runs from other roots of one graph have similar depth),
-    // so most runs end inside it with few idle launches and one wait.
-    int lvl = 0;
-    int chunk = std::max(8, std::min(64, w->last_launches + 1));
+    // Steps are enqueued in chunks; between chunks the host reads the done
+    // flag. A step is the small-level kernel (which advances the level and runs
+    // any small levels), then one expansion and one restoration; the level
+    // each works on lives in the control block. The first chunk covers as many
+    // steps as the previous run on this workspace used (runs from other roots
+    // of one graph have similar shapes), so most runs end inside it.
+    // Without the small-level kernel a step is one level, passed as an argument.
+    const bool small = p.s_max > 0;
+    int64_t steps = 0;
+    int chunk = std::max(4, std::min(64, w->last_launches + 1));
     while (true) {
         for (int i = 0; i < chunk; ++i) {
-            k_expand<OffT, BLOCK, kAtomic><<<gr.expand, BLOCK, (size_t)lds_words * 4, s>>>(p, lvl + i);
-            k_restore<OffT, kAtomic><<<gr.restore, kRestoreBlock, 0, s>>>(p, lvl + i);
+            const int lvl = small ? -1 : (int)(steps + i);
+            if (small) k_small<OffT><<<1, kSmallBlock, 0, s>>>(p);
+            k_expand<OffT, BLOCK, kAtomic><<<gr.expand, BLOCK, (size_t)lds_words * 4, s>>>(p, lvl);
+            k_restore<OffT, kAtomic><<<gr.restore, kRestoreBlock, 0, s>>>(p, lvl);
         }
         BFS_HIP(hipGetLastError());
-        lvl += chunk;
-        static_assert(offsetof(Ctrl, num_levels) == offsetof(Ctrl, done) + sizeof(int), "done, then num_levels");
-        BFS_HIP(hipMemcpyAsync(&w->host_ctrl->done, &p.ctrl->done, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+        steps += chunk;
+        static_assert(offsetof(Ctrl, steps) == offsetof(Ctrl, done) + 3 * sizeof(int), "done .. steps");
+        BFS_HIP(hipMemcpyAsync(&w->host_ctrl->done, &p.ctrl->done, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
         BFS_HIP(hipStreamSynchronize(s));
-        if (w->host_ctrl->done || lvl > p.n + 1) break;
+        if (w->host_ctrl->done || steps > p.n + 1) break;
         chunk = chunk < 64 ? chunk * 2 : 64;
     }
-    // The level that found the frontier empty was the last launch with work.
-    if (w->host_ctrl->done) w->last_launches = w->host_ctrl->num_levels + 1;
+    // The step that found the frontier empty was the last one with work.
+    if (w->host_ctrl->done) w->last_launches = small ? w->host_ctrl->steps : w->host_ctrl->num_levels + 1;
     if (p.new2old) {
         const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((p.n + 255) / 256, (int64_t)g->cu_count * 16));
         k_out<<<blocks, 256, 0, s>>>(reinterpret_cast<const int2*>(p.lv), p.new2old, p.out_lv, p.out_pa, p.n);
@@ -1279,6 +1496,11 @@ void launch_single(bfs_graph* g, const bfs_tunables& t, Workspace* w, int32_t ro
     if (hybrid && !g->symmetric) fail(BFS_E_INVALID_ARG, "bottom-up levels need a graph loaded as symmetric");
     p.nnz = g->nnz;
     p.hybrid = hybrid ? 1 : 0;
+    p.sl = w->sl;
+    p.sl_cnt = w->sl_cnt;
+    p.s_max = t.sparse_frontier > 0 ? std::min(t.sparse_frontier, kSmallMax) : 0;
+    p.s_arcs = (int64_t)p.s_max * 4;
+    if (!p.sl || !p.sl_cnt || g->restore_grid > kSmallBlock) fail(BFS_E_INTERNAL, "small-level lists out of range");
     const bool off32 = !h && g->off32;
     const bool atomic = t.update_mode == 2;
 #define BFS_LAUNCH(OFFT, BS)                                         \

@@ -106,6 +106,9 @@ def test_device_pointer_graph():
     dict(lds_visited=1, block_size=256, small_max_degree=8, wave_max_degree=32),
     dict(lds_visited=1, block_size=512, update_mode=2),
     dict(lds_visited=-1, block_size=1024),
+    dict(sparse_frontier=-1),                                   # every level through the grid kernels
+    dict(sparse_frontier=1),                                    # the single-workgroup path for 1-vertex frontiers only
+    dict(sparse_frontier=64, update_mode=2),
 ])
 def test_bins_and_launch_shapes(tun):
     """Correctness does not depend on the degree bins or the launch shape."""
@@ -224,3 +227,18 @@ def test_lds_visited_defaults_and_limit():
     with pytest.raises(bfs.BfsError) as e:
         bfs.bfs_graph_set_tunables(big, lds_visited=1, block_size=1024)
     assert e.value.status == bfs.BFS_E_INVALID_ARG
+
+
+@pytest.mark.parametrize("sparse", [-1, 0, 3, 100])
+def test_small_level_kernel_shapes(sparse):
+    """Long chains of small levels (paths, a cycle, a binary tree, a star whose
+    leaves all land in one restore block's list, a broom: a path into a big
+    star) give the same levels and valid parents with the single-workgroup
+    level kernel off, at its default, and at tight limits."""
+    cases = [(graphgen.path(3000), 0), (graphgen.path(3000), 1500), (graphgen.cycle(2001), 5),
+             (graphgen.binary_tree(1 << 13), 0), (graphgen.star(5000), 0), (graphgen.star(5000), 17),
+             (graphgen.from_edges(3000, list(range(999)) + [999] * 2000, list(range(1, 1000)) + list(range(1000, 3000))), 0)]
+    for g, r in cases:
+        dg = load(g)
+        bfs.bfs_graph_set_tunables(dg, sparse_frontier=sparse)
+        check_root(g, dg, r)

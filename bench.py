@@ -60,8 +60,8 @@ def parse():
                     help="also run a plain copy kernel of BYTES (read and written) for counter scaling")
     ap.add_argument("--mode", default="single", choices=["single", "batch", "serve"])
     ap.add_argument("--rates", default="1000,5000,10000,20000,50000", help="serve: arrival rates (queries/s)")
-    ap.add_argument("--queries", type=int, default=20000, help="serve: queries per rate")
-    ap.add_argument("--warmup-queries", type=int, default=2000, help="serve: leading queries left out of the stats")
+    ap.add_argument("--queries", type=int, default=4000, help="serve: queries per rate")
+    ap.add_argument("--warmup-queries", type=int, default=400, help="serve: leading queries left out of the stats")
     return ap.parse_args()
 
 

@@ -228,17 +228,25 @@ __device__ __forceinline__ bool lds_slot(const LdsVis& l, int32_t v, uint32_t& b
 template <bool kAtomic, int U>
 __device__ __forceinline__ void visit_arcs(const SingleParams& p, const int64_t (&pos)[U], const bool (&ok)[U],
                                            const int32_t (&par)[U], int lvl, const LdsVis& lds) {
+    // Loads are issued by every lane, so no lane mask is set up around them:
+    // callers hand idle lanes a valid position (a repeat of a real arc), and
+    // lanes with nothing to probe read one shared dummy word (one request per
+    // wavefront instruction) and discard it.
     int32_t v[U];
 #pragma unroll
-    for (int i = 0; i < U; ++i) v[i] = ok[i] ? __builtin_nontemporal_load(p.col + pos[i]) : 0;
+    for (int i = 0; i < U; ++i) v[i] = __builtin_nontemporal_load(p.col + pos[i]);
     uint32_t w[U];
     bool in_lds[U];
     uint32_t slot[U];
+    const bool lds_on = (lds.hot_limit | lds.full_words) != 0;  // the same for the whole workgroup
 #pragma unroll
     for (int i = 0; i < U; ++i) {
         in_lds[i] = ok[i] && lds_slot(lds, v[i], slot[i]);
-        const bool known = in_lds[i] && ((lds.bits[slot[i] >> 5] >> (slot[i] & 31)) & 1u);
-        w[i] = (ok[i] && !known) ? p.vis[(uint32_t)v[i] >> 5] : ~0u;
+        const uint32_t lw = lds_on ? lds.bits[in_lds[i] ? slot[i] >> 5 : 0] : 0u;
+        const bool known = in_lds[i] && ((lw >> (slot[i] & 31)) & 1u);
+        const bool need = ok[i] && !known;
+        const uint32_t x = p.vis[need ? (uint32_t)v[i] >> 5 : 0u];
+        w[i] = need ? x : ~0u;
     }
     if (kAtomic) {
         uint32_t old[U];
@@ -263,7 +271,11 @@ __device__ __forceinline__ void visit_arcs(const SingleParams& p, const int64_t 
         // reached in any earlier level.
         int lv_now[U];
 #pragma unroll
-        for (int i = 0; i < U; ++i) lv_now[i] = (!(w[i] & (1u << (v[i] & 31)))) ? ld(p.lv + lv_at(p, v[i])) : 0;
+        for (int i = 0; i < U; ++i) {
+            const bool cand = !(w[i] & (1u << (v[i] & 31)));
+            const int x = ld(p.lv + (cand ? lv_at(p, v[i]) : 0));
+            lv_now[i] = cand ? x : 0;
+        }
 #pragma unroll
         for (int i = 0; i < U; ++i) {
             const uint32_t b = 1u << (v[i] & 31);
@@ -287,7 +299,7 @@ __device__ __forceinline__ void expand_row(const SingleParams& p, int64_t beg, i
         for (int i = 0; i < U; ++i) {
             const int64_t j = j0 + (int64_t)i * nthreads + t;
             ok[i] = j < d;
-            pos[i] = beg + j;
+            pos[i] = beg + (ok[i] ? j : d - 1);  // idle lanes repeat the row's last arc
             par[i] = u;
         }
         visit_arcs<kAtomic, U>(p, pos, ok, par, lvl, lds);
@@ -341,10 +353,11 @@ __device__ __forceinline__ void process_batch(const SingleParams& p, int32_t u, 
             const int from_map = __shfl(here, last, 64);
             const int e = m ? from_map : open;
             open = __shfl(e, 63, 64);
+            // Lanes past the batch's last arc repeat it (their row is the last one).
             ok[i] = base + i * 64 + lane < total;
-            const int ec = ok[i] ? e : 0;
-            pos[i] = shfl64(rbase, ec) + (base + i * 64 + lane);
-            par[i] = __shfl(uo, ec, 64);
+            const int ac = ok[i] ? base + i * 64 + lane : total - 1;
+            pos[i] = shfl64(rbase, e) + ac;
+            par[i] = __shfl(uo, e, 64);
         }
         visit_arcs<kAtomic, kLbsUnroll>(p, pos, ok, par, lvl, lds);
     }

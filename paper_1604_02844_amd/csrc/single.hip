@@ -397,9 +397,10 @@ struct ExpandShared {
 // Rows above T2: this workgroup's share [a0, a1) of the level's concatenated
 // big-row arcs. Row metadata is staged BLOCK rows at a time (every thread loads
 // one row); each wavefront then takes a contiguous run of those arcs, 64 x
-// kBigUnroll consecutive arcs per step, so column reads are coalesced and a
-// lane finds its row by moving a cursor forward over the staged starts (rows
-// above T2 are long, so the cursor seldom moves) instead of searching anew.
+// kBigUnroll consecutive arcs per step, so column reads are coalesced. The
+// row boundaries inside a step come from one LDS read per lane (the next 64
+// staged starts) and a ballot; rows above T2 are long, so a step crosses at
+// most a few, and no lane runs a search or a loop of its own.
 template <typename OffT, bool kAtomic, int BLOCK>
 __device__ __forceinline__ void expand_big(const SingleParams& p, ExpandShared<BLOCK>& sh, int64_t a0, int64_t a1,
                                            int lvl, unsigned long long& arcs, const LdsVis& lds) {
@@ -499,22 +500,56 @@ __device__ __forceinline__ void expand_big(const SingleParams& p, ExpandShared<B
                 const int mid = (lo + hi + 1) >> 1;
                 if (sh.x.big.start[mid] <= w_lo) lo = mid; else hi = mid - 1;
             }
-            int row = lo;
-            for (int64_t ws = w_lo; ws < w_hi; ws += 64 * kBigUnroll) {
+            int row = lo;  // the same in every lane
+            constexpr int SPAN = 64 * kBigUnroll;
+            for (int64_t ws = w_lo; ws < w_hi; ws += SPAN) {
+                // The next 64 staged row starts, one per lane: those inside this
+                // span are the row boundaries the span crosses (sorted, and few:
+                // rows above T2 are long).
+                const int nr = row + 1 + lane;
+                const int64_t x = nr < nt ? sh.x.big.start[nr] : INT64_MAX;
+                const uint64_t inside = __ballot(x < ws + SPAN);
+                const int k = __popcll(inside);  // boundaries before the span's end, all in lanes 0..k-1
                 int64_t pos[kBigUnroll];
                 bool ok[kBigUnroll];
                 int32_t par[kBigUnroll];
-                int r = row;
+                int r[kBigUnroll];
+#pragma unroll
+                for (int i = 0; i < kBigUnroll; ++i) r[i] = row;
+                int next_row;
+                if (k < 64) {
+                    for (int j = 0; j < k; ++j) {  // the same trip count in every lane
+                        const int64_t bj = shfl64(x, j);
+#pragma unroll
+                        for (int i = 0; i < kBigUnroll; ++i) {
+                            const int64_t a = ws + i * 64 + lane;
+                            r[i] += (a < w_hi ? a : w_hi - 1) >= bj ? 1 : 0;
+                        }
+                    }
+                    next_row = row + __popcll(__ballot(x <= ws + SPAN));
+                } else {
+                    // More than 64 rows in one span (only with a very small T2):
+                    // each lane moves its own cursor forward.
+#pragma unroll
+                    for (int i = 0; i < kBigUnroll; ++i) {
+                        const int64_t a = ws + i * 64 + lane;
+                        const int64_t ac = a < w_hi ? a : w_hi - 1;
+                        int rr = i == 0 ? row : r[i - 1];
+                        while (rr + 1 < nt && sh.x.big.start[rr + 1] <= ac) ++rr;
+                        r[i] = rr;
+                    }
+                    next_row = __shfl(r[kBigUnroll - 1], 63, 64);
+                    while (next_row + 1 < nt && sh.x.big.start[next_row + 1] <= ws + SPAN) ++next_row;
+                }
 #pragma unroll
                 for (int i = 0; i < kBigUnroll; ++i) {
                     const int64_t a = ws + i * 64 + lane;
                     ok[i] = a < w_hi;
                     const int64_t ac = ok[i] ? a : w_hi - 1;
-                    while (r + 1 < nt && sh.x.big.start[r + 1] <= ac) ++r;
-                    pos[i] = sh.x.big.base[r] + ac;
-                    par[i] = sh.x.big.u[r];
+                    pos[i] = sh.x.big.base[r[i]] + ac;
+                    par[i] = sh.x.big.u[r[i]];
                 }
-                row = __shfl(r, 63, 64);
+                row = next_row;  // the row of the next span's first arc
                 visit_arcs<kAtomic, kBigUnroll>(p, pos, ok, par, lvl, lds);
             }
         }

@@ -54,8 +54,8 @@ namespace bfs {
 namespace {
 
 constexpr int kUnroll = 2;     // arcs per lane in flight: one wavefront per row (T1 < d <= T2)
-constexpr int kLbsUnroll = 4;  // arcs per lane in flight: packed rows (d <= T1)
-constexpr int kBigUnroll = 4;  // arcs per lane in flight: rows above T2
+constexpr int kLbsUnroll = 8;  // arcs per lane in flight: packed rows (d <= T1)
+constexpr int kBigUnroll = 8;  // arcs per lane in flight: rows above T2
 constexpr int kBuFirst = 4;       // bottom-up: arcs each lane checks before its wavefront helps
 constexpr int kSmallBlock = 1024;  // threads of the small-level kernel
 

@@ -58,6 +58,7 @@ constexpr int kLbsUnroll = 8;  // arcs per lane in flight: packed rows (d <= T1)
 constexpr int kBigUnroll = 8;  // arcs per lane in flight: rows above T2
 constexpr int kBuFirst = 4;       // bottom-up: arcs each lane checks before its wavefront helps
 constexpr int kSmallBlock = 1024;  // threads of the small-level kernel
+constexpr int kRebuildPairs = 8;   // restore: pairs of touched words whose levels are read per round
 
 struct SingleParams {
     const void* off;
@@ -987,23 +988,33 @@ __global__ __launch_bounds__(kRestoreBlock) void k_restore(SingleParams p, int l
             // one of its bits set: the level array says exactly who was
             // discovered. Two touched words per step: each half-wave reads
             // one word's 32 levels.
+            // Up to kRebuildPairs pairs of touched words per round, all their
+            // level reads in flight together.
             uint64_t tm = __ballot(touched);
             const int64_t wave_w0 = c * BLOCK + (tid & ~63);
             while (tm) {
-                const int wa = __builtin_ctzll(tm);
-                tm &= tm - 1;
-                int wb = -1;
-                if (tm) {
-                    wb = __builtin_ctzll(tm);
+                int wa[kRebuildPairs], wb[kRebuildPairs], lvv[kRebuildPairs];
+#pragma unroll
+                for (int k = 0; k < kRebuildPairs; ++k) {
+                    wa[k] = tm ? __builtin_ctzll(tm) : -1;
+                    tm &= tm - 1;
+                    wb[k] = tm ? __builtin_ctzll(tm) : -1;
                     tm &= tm - 1;
                 }
-                const int src = lane < 32 ? wa : wb;
-                const int64_t v = (wave_w0 + src) * 32 + (lane & 31);
-                const bool okl = src >= 0 && v < p.n;
-                const int lvv = okl ? ld(p.lv + lv_at(p, v)) : -1;
-                const uint64_t m = __ballot(lvv == next);
-                if (lane == wa) exact = (uint32_t)m;
-                if (lane == wb) exact = (uint32_t)(m >> 32);
+#pragma unroll
+                for (int k = 0; k < kRebuildPairs; ++k) {
+                    const int src = lane < 32 ? wa[k] : wb[k];
+                    const int64_t v = (wave_w0 + src) * 32 + (lane & 31);
+                    const bool okl = src >= 0 && v < p.n;
+                    const int x = ld(p.lv + (okl ? lv_at(p, v) : 0));
+                    lvv[k] = okl ? x : -1;
+                }
+#pragma unroll
+                for (int k = 0; k < kRebuildPairs; ++k) {
+                    const uint64_t m = __ballot(lvv[k] == next);
+                    if (lane == wa[k]) exact = (uint32_t)m;
+                    if (lane == wb[k]) exact = (uint32_t)(m >> 32);
+                }
             }
         }
         if (touched) {

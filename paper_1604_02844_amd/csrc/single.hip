@@ -391,6 +391,8 @@ struct ExpandShared {
     unsigned long long red[NW];
     unsigned long long found;
     unsigned long long big_total;
+    unsigned long long seen;  // hybrid runs: vertices visited before this frontier
+    int was_bu;               // hybrid runs: the previous level ran bottom-up
     int64_t staged_end;  // last arc (exclusive) of the staged big rows
     uint32_t row0;
 };
@@ -798,12 +800,25 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl_arg) {
     if (lvl_arg < 0 && ld(&p.ctrl->skip_e)) return;
     const int lvl = lvl_arg >= 0 ? lvl_arg : ld(&p.ctrl->level);
 
-    // Termination: the restore pass of the previous level counted this frontier.
+    // Termination, and the arcs of the frontier's rows above T2: both counted
+    // by the previous restore, read in one round.
     if (tid < 64) {
         unsigned long long c = ld(stripe(p.ctrl, lvl & 1, tid));
+        unsigned long long b = ld(&p.ctrl->bigarcs[lvl & 1][tid * kStripeStride]);
         c = wave_sum(c);
-        if (tid == 0) sh.found = c;
-        if (bid == 0) st(stripe(p.ctrl, (lvl + 1) & 1, tid), 0ull);  // counters for the next level
+        b = wave_sum(b);
+        if (tid == 0) {
+            sh.found = c;
+            sh.big_total = b;
+            if (p.hybrid) {
+                sh.was_bu = ld(&p.ctrl->dir[lvl & 1]);
+                sh.seen = ld(&p.ctrl->visited[lvl & 1]);
+            }
+        }
+        if (bid == 0) {  // counters for the next level
+            st(stripe(p.ctrl, (lvl + 1) & 1, tid), 0ull);
+            st(&p.ctrl->bigarcs[(lvl + 1) & 1][tid * kStripeStride], 0ull);
+        }
     }
     __syncthreads();
     if (sh.found == 0) {
@@ -814,23 +829,14 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl_arg) {
         return;
     }
     unsigned long long arcs = 0;
-
-    // Arcs of the frontier's rows above T2 (counted by the previous restore).
-    if (tid < 64) {
-        unsigned long long c = ld(&p.ctrl->bigarcs[lvl & 1][tid * kStripeStride]);
-        c = wave_sum(c);
-        if (tid == 0) sh.big_total = c;
-        if (bid == 0) st(&p.ctrl->bigarcs[(lvl + 1) & 1][tid * kStripeStride], 0ull);
-    }
-    __syncthreads();
     const int64_t ta = (int64_t)sh.big_total;
 
     // ---- direction (hybrid runs): every workgroup decides the same from the
     // same counters. Bottom-up once the frontier's arcs exceed 1/14 of the arcs
     // still unvisited; back to top-down when the frontier falls below n/24.
     if (p.hybrid) {
-        const bool was_bu = ld(&p.ctrl->dir[lvl & 1]) != 0;
-        const unsigned long long seen = ld(&p.ctrl->visited[lvl & 1]);
+        const bool was_bu = sh.was_bu != 0;
+        const unsigned long long seen = sh.seen;
         const double nf = (double)sh.found;
         const double mf = (double)ta + nf * ((double)p.nnz / (double)p.n);
         const double unvisited = (double)p.n - (double)seen - nf;

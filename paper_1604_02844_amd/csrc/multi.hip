@@ -37,6 +37,7 @@ typedef unsigned long long u64;
 
 constexpr int kUnroll = 2;
 constexpr int kPullUnroll = 4;
+constexpr int kPullHead = 16;  // arcs a lane scans on its own before its wavefront helps
 constexpr int kPushAlpha = 12;  // push while (arcs of the frontier rows) * alpha < nnz
 
 struct MsParams {
@@ -369,50 +370,99 @@ __global__ __launch_bounds__(BLOCK) void k_ms_push(MsParams p, int lvl) {
 // pull
 // ---------------------------------------------------------------------------
 
+// Exclusive prefix OR of x over the lanes below this one.
+__device__ __forceinline__ u64 wave_excl_or(u64 x, int lane) {
+    u64 incl = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int lo = __shfl_up((int)(uint32_t)incl, d, 64);
+        const int hi = __shfl_up((int)(uint32_t)(incl >> 32), d, 64);
+        if (lane >= d) incl |= ((u64)(uint32_t)hi << 32) | (uint32_t)lo;
+    }
+    const int lo = __shfl_up((int)(uint32_t)incl, 1, 64);
+    const int hi = __shfl_up((int)(uint32_t)(incl >> 32), 1, 64);
+    return lane == 0 ? 0ull : (((u64)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Each vertex still missing roots gathers its neighbours' frontier masks
+// until every missing root is found. A lane scans the head of its own row;
+// rows still open after it are scanned by the whole wavefront, 64 arcs at a
+// time (coalesced column reads), so a hub row does not hold one lane for its
+// whole length. A root bit found in several arcs of a step takes the lowest
+// lane's neighbour as parent.
 template <typename OffT>
 __global__ __launch_bounds__(256) void k_ms_pull(MsParams p, int lvl) {
     if (ld(&p.ctrl->done)) return;
-    const LevelView lv = read_level(p.ctrl, lvl);
-    if (lv.disc == 0 || choose_push(p, lv)) return;
-    const u64 alive = lv.alive;
-    const int64_t gsize = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < p.n; v += gsize) {
-        const u64 seen = ld(p.vis + v);
+    const LevelView lview = read_level(p.ctrl, lvl);
+    if (lview.disc == 0 || choose_push(p, lview)) return;
+    const u64 alive = lview.alive;
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t base = wave * 64; base < p.n; base += waves * 64) {
+        const int64_t v = base + lane;
+        const bool valid = v < p.n;
+        const u64 seen = valid ? ld(p.vis + v) : ~0ull;
         const u64 miss = alive & ~seen;
         u64 acc = 0;
+        int64_t beg = 0, end = 0;
         if (miss) {
-            const int64_t beg = load_off<OffT>(p.off, v);
-            const int64_t end = load_off<OffT>(p.off, v + 1);
-            for (int64_t j = beg; j < end && acc != miss; j += kPullUnroll) {
-                int32_t u[kPullUnroll];
-                u64 f[kPullUnroll];
+            beg = load_off<OffT>(p.off, v);
+            end = load_off<OffT>(p.off, v + 1);
+        }
+        const int64_t head_end = end - beg > kPullHead ? beg + kPullHead : end;
+        for (int64_t j = beg; j < head_end && acc != miss; j += kPullUnroll) {
+            int32_t u[kPullUnroll];
+            u64 f[kPullUnroll];
 #pragma unroll
-                for (int q = 0; q < kPullUnroll; ++q) u[q] = j + q < end ? p.col[j + q] : -1;
+            for (int q = 0; q < kPullUnroll; ++q) u[q] = j + q < head_end ? p.col[j + q] : -1;
 #pragma unroll
-                for (int q = 0; q < kPullUnroll; ++q) f[q] = u[q] >= 0 ? ld(p.fr + u[q]) : 0ull;
+            for (int q = 0; q < kPullUnroll; ++q) f[q] = u[q] >= 0 ? ld(p.fr + u[q]) : 0ull;
 #pragma unroll
-                for (int q = 0; q < kPullUnroll; ++q) {
-                    const u64 nb = f[q] & miss & ~acc;
-                    if (nb) {
-                        acc |= nb;
-                        u64 b = nb;
-                        while (b) {
-                            const int i = __builtin_ctzll(b);
-                            b &= b - 1;
-                            ld(&p.ctrl->out_pa[i])[v] = u[q];
-                        }
+            for (int q = 0; q < kPullUnroll; ++q) {
+                const u64 nb = f[q] & miss & ~acc;
+                if (nb) {
+                    acc |= nb;
+                    u64 b = nb;
+                    while (b) {
+                        const int i = __builtin_ctzll(b);
+                        b &= b - 1;
+                        ld(&p.ctrl->out_pa[i])[v] = u[q];
                     }
                 }
             }
         }
-        st(p.nfr + v, acc);
-        if (acc) {
-            st(p.vis + v, seen | acc);
-            u64 b = acc;
-            while (b) {
-                const int i = __builtin_ctzll(b);
-                b &= b - 1;
-                ld(&p.ctrl->out_lv[i])[v] = lvl + 1 - ld(&p.ctrl->start[i]);
+        // Rows still open: one at a time, by the whole wavefront.
+        uint64_t open = __ballot(acc != miss && head_end < end);
+        while (open) {
+            const int src = __builtin_ctzll(open);
+            open &= open - 1;
+            const int64_t lb = (int64_t)shflu64((u64)head_end, src), le = (int64_t)shflu64((u64)end, src);
+            const u64 m = shflu64(miss, src);
+            const int32_t vs = (int32_t)(base + src);
+            u64 a = shflu64(acc, src);
+            for (int64_t j0 = lb; j0 < le && a != m; j0 += 64) {
+                const int64_t j = j0 + lane;
+                const bool in_row = j < le;
+                const int32_t u = p.col[in_row ? j : le - 1];
+                const u64 f = ld(p.fr + u);
+                const u64 nb = in_row ? (f & m & ~a) : 0ull;
+                const u64 mine = nb & ~wave_excl_or(nb, lane);
+                for (u64 b = mine; b; b &= b - 1) ld(&p.ctrl->out_pa[__builtin_ctzll(b)])[vs] = u;
+                a |= wave_or(nb);
+            }
+            if (lane == src) acc = a;
+        }
+        if (valid) {
+            st(p.nfr + v, acc);
+            if (acc) {
+                st(p.vis + v, seen | acc);
+                u64 b = acc;
+                while (b) {
+                    const int i = __builtin_ctzll(b);
+                    b &= b - 1;
+                    ld(&p.ctrl->out_lv[i])[v] = lvl + 1 - ld(&p.ctrl->start[i]);
+                }
             }
         }
     }

@@ -36,8 +36,8 @@ namespace {
 typedef unsigned long long u64;
 
 constexpr int kUnroll = 2;
-constexpr int kPullUnroll = 4;
-constexpr int kPullHead = 16;  // arcs a lane scans on its own before its wavefront helps
+constexpr int kPullUnroll = 8;
+constexpr int kPullHead = 32;  // arcs a lane scans on its own before its wavefront helps
 constexpr int kPushAlpha = 12;  // push while (arcs of the frontier rows) * alpha < nnz
 
 struct MsParams {

@@ -112,3 +112,21 @@ def test_er_batches_8_32_64():
     pool = graphgen.pick_roots(g, 64, seed=40)
     for b in (8, 32, 64):
         check_batch(g, dg, pool[:b])
+
+
+def test_pull_long_rows():
+    """Dense levels where rows longer than a lane's head are scanned by the
+    whole wavefront: a star whose hub is reached from 64 leaf roots, a complete
+    graph, two hubs joined by a path (the scan must run past early windows
+    that find nothing), and R-MAT with 64 roots."""
+    star = graphgen.star(5000)
+    check_batch(star, load(star), list(range(1, 65)))
+    comp = graphgen.complete(300)
+    check_batch(comp, load(comp), list(range(0, 300, 5))[:64])
+    n = 6000
+    src = [0] * 2000 + [5999] * 2000 + list(range(2000, 3999))
+    dst = list(range(1, 2001)) + list(range(3000, 5000)) + list(range(2001, 4000))
+    broom = graphgen.from_edges(n, src, dst)
+    check_batch(broom, load(broom), [1, 2, 3, 4999, 4998, 2500, 3500, 0, 5999])
+    g = graphgen.rmat(16, 16, seed=39)
+    check_batch(g, load(g), graphgen.pick_roots(g, 64, seed=40))

@@ -110,7 +110,10 @@ typedef struct {
                                    this many vertices (the highest-degree ones, taken from a
                                    degree-ordered copy of the graph) in LDS during levels with
                                    large frontiers and probes them there first; rounded up to
-                                   a multiple of 2048; -1 = off, 0 = library default */
+                                   a multiple of 64 and capped at 2^20 and at two per full
+                                   32-vertex word (one per word while they fit, else two);
+                                   -1 = off, 0 = library default (2^20 from 2^22 vertices on
+                                   skewed graphs) */
     int32_t lds_visited;        /* single-root runs without the degree-ordered copy: every
                                    workgroup copies the whole visited bitmap (bottom-up levels:
                                    the whole frontier bitmap) into LDS at the start of a level

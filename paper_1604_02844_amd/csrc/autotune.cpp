@@ -129,7 +129,7 @@ void autotune(bfs_graph* g, const int32_t* roots, int32_t num_roots, int32_t mod
     };
     std::vector<Axis> axes;
     if (mode == 0) {
-        axes = {{&bfs_tunables::hot_vertices, {-1, 1 << 17, 1 << 19}},
+        axes = {{&bfs_tunables::hot_vertices, {-1, 1 << 18, 1 << 19, 1 << 20}},
                 {&bfs_tunables::block_size, {256, 512, 1024}},
                 {&bfs_tunables::update_mode, {1, 2}},
                 {&bfs_tunables::wave_max_degree, {64, 128, 256, 512, 1024}},

@@ -148,8 +148,16 @@ struct BigTable {
 // visited bits form a compact bitmap that fits in LDS. Every other vertex keeps
 // its relative order, so frontier words stay as evenly loaded as in the
 // caller's order. Offsets are int64; outputs are written at caller ids.
+// Hot vertices of the degree-ordered copy: degree rank s (0 = highest) sits
+// at bit position (s / span) << shift of visited word s % span, so each of the
+// first span = hot >> (5 - shift) words holds one hot vertex (shift 5) or two,
+// at bits 0 and 16 (shift 4). The compact hot bitmaps use bit s.
+inline int hot_shift_for(int64_t n, int64_t hot) { return hot <= n / 32 ? 5 : 4; }
+
 struct HotLayout {
     int32_t hot = 0;
+    int32_t shift = 5;  // hot_shift_for(n, hot)
+    int32_t span = 0;   // visited words holding hot vertices
     int64_t* d_off = nullptr;       // [n+1], new order
     int32_t* d_col = nullptr;       // [nnz], new ids
     int32_t* d_new2old = nullptr;   // [n]
@@ -206,7 +214,7 @@ void build_hot_layout(bfs_graph* g, int32_t hot, int32_t threshold);
 void free_hot_layout(bfs_graph* g);
 // Device part of the copy (single.hip): new columns of every new row.
 void launch_relabel_cols(const bfs_graph* g, const int64_t* d_noff, const int32_t* d_new2old,
-                         const int32_t* d_old2new, int32_t* d_ncol, int32_t hot);
+                         const int32_t* d_old2new, int32_t* d_ncol, int32_t hot_span, int32_t hot_shift);
 int64_t padded_words(int64_t n);
 // Most visited-bitmap words an expansion workgroup of `block` threads can hold
 // in LDS beside its static shared memory.

@@ -140,9 +140,10 @@ void build_big_table(BigTable& t, const void* d_off, bool off32, int64_t n, int3
 
 int32_t hot_count(const bfs_graph* g, const bfs_tunables& t) {
     if (t.hot_vertices <= 0) return 0;
-    int64_t h = ((int64_t)t.hot_vertices + 2047) / 2048 * 2048;  // whole 64-bit words of the compact bitmap
+    // Whole 64-bit words of the compact bitmap, at most two per full visited word.
+    int64_t h = ((int64_t)t.hot_vertices + 63) / 64 * 64;
     h = std::min<int64_t>(h, (int64_t)kMaxHotWords * 32);
-    h = std::min<int64_t>(h, (g->n + 31) / 32);                   // ids 32r must exist
+    h = std::min<int64_t>(h, g->n / 32 * 2 / 64 * 64);
     return (int32_t)std::max<int64_t>(h, 0);
 }
 
@@ -158,8 +159,9 @@ void free_hot_layout(bfs_graph* g) {
 }
 
 // The degree-ordered copy. Hot vertices: the `hot` highest degrees (ties to
-// the lower id), placed at ids 32r by decreasing degree; all other vertices
-// fill the remaining ids in increasing caller-id order. Columns are renamed on
+// the lower id), by decreasing degree at bit 0 of the first `span` visited
+// words, then (when they need two per word) at bit 16 of the same words; all
+// other vertices fill the remaining ids in increasing caller-id order. Columns are renamed on
 // the device and every row lists its hot neighbours first (each part in the
 // original arc order), so a bottom-up scan meets the likely parents first.
 void build_hot_layout(bfs_graph* g, int32_t hot, int32_t threshold) {
@@ -191,11 +193,15 @@ void build_hot_layout(bfs_graph* g, int32_t hot, int32_t threshold) {
     std::stable_sort(hot_ids.begin(), hot_ids.end(), [&](int32_t a, int32_t b) {
         return off[(size_t)a + 1] - off[(size_t)a] > off[(size_t)b + 1] - off[(size_t)b];
     });
+    const int shift = hot_shift_for(n, hot);
+    const int64_t span = (int64_t)(hot / 32) << shift;
+    if (hot % 64 != 0 || span * 32 > n) fail(BFS_E_INTERNAL, "hot set does not fit the visited words");
     std::vector<int32_t> new2old((size_t)n), old2new((size_t)n);
     int64_t cold = 0;
     for (int64_t x = 0; x < n; ++x) {
-        if ((x & 31) == 0 && (x >> 5) < hot) {
-            new2old[(size_t)x] = hot_ids[(size_t)(x >> 5)];
+        // Position k = (x & 31) >> shift of word x >> 5 holds rank (x >> 5) + k * span.
+        if ((x & ((1 << shift) - 1)) == 0 && (x >> 5) < span) {
+            new2old[(size_t)x] = hot_ids[(size_t)((x >> 5) + ((x & 31) >> shift) * span)];
         } else {
             while (is_hot[(size_t)cold]) ++cold;
             new2old[(size_t)x] = (int32_t)cold++;
@@ -209,6 +215,8 @@ void build_hot_layout(bfs_graph* g, int32_t hot, int32_t threshold) {
     }
     auto h = std::make_unique<HotLayout>();
     h->hot = hot;
+    h->shift = shift;
+    h->span = (int32_t)span;
     int32_t* d_old2new = nullptr;
     try {
         BFS_HIP(hipMalloc(&h->d_off, noff.size() * 8));
@@ -218,7 +226,7 @@ void build_hot_layout(bfs_graph* g, int32_t hot, int32_t threshold) {
         BFS_HIP(hipMemcpy(h->d_off, noff.data(), noff.size() * 8, hipMemcpyHostToDevice));
         BFS_HIP(hipMemcpy(h->d_new2old, new2old.data(), (size_t)n * 4, hipMemcpyHostToDevice));
         BFS_HIP(hipMemcpy(d_old2new, old2new.data(), (size_t)n * 4, hipMemcpyHostToDevice));
-        launch_relabel_cols(g, h->d_off, h->d_new2old, d_old2new, h->d_col, hot);
+        launch_relabel_cols(g, h->d_off, h->d_new2old, d_old2new, h->d_col, h->span, h->shift);
         BFS_HIP(hipDeviceSynchronize());
         BFS_HIP(hipFree(d_old2new));
         d_old2new = nullptr;
@@ -291,12 +299,13 @@ bfs_tunables default_tunables(const bfs_graph* g) {
     t.batch_width = 64;
     t.update_mode = 1;
     // From 2^22 vertices on, single-root runs use the degree-ordered copy with
-    // an LDS bitmap of the 2^19 highest-degree vertices (64 KiB), shared by the
-    // 16 wavefronts of a 1024-thread workgroup.
+    // an LDS bitmap of the 2^20 highest-degree vertices (128 KiB; fewer below
+    // 2^25 vertices, at most two per visited word), shared by the 16
+    // wavefronts of a 1024-thread workgroup.
     // Only skewed degree distributions concentrate probes on few vertices.
     const bool large = g && g->n >= (int64_t)1 << 22 &&
                        g->max_degree > 64 * std::max<int64_t>(1, g->nnz / std::max<int64_t>(1, g->n));
-    t.hot_vertices = large ? 1 << 19 : -1;
+    t.hot_vertices = large ? 1 << 20 : -1;
     if (large) t.block_size = 1024;
     // Up to 2^20 vertices the whole visited bitmap (128 KiB) fits in the LDS
     // of a 1024-thread workgroup instead.
@@ -359,7 +368,7 @@ Workspace* acquire_ws(bfs_graph* g, hipStream_t s) {
         w->big_capacity = std::max(g->big.num_big, 1);
         const size_t bmb = (size_t)w->words * 4;
         const size_t listb = (size_t)w->big_capacity * 8 + (size_t)(g->restore_grid + 1) * 8;
-        w->hot_capacity = (int)std::min<int64_t>(w->words / 32, kMaxHotWords);
+        w->hot_capacity = (int)std::min<int64_t>(w->words / 16, kMaxHotWords);
         const size_t hotb = (size_t)w->hot_capacity * 8;  // visited and frontier bits
         const size_t recb = g->hot ? (size_t)g->n * 8 : 0;  // {level, parent} in the degree-ordered ids
         const size_t smallb = (size_t)g->restore_grid * (kSmallSeg + 1) * 4;  // listed small frontiers

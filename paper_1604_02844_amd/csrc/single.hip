@@ -90,12 +90,16 @@ struct SingleParams {
     int32_t restore_grid;
     int32_t t1;
     int32_t min_share;         // fewest big-row arcs handed to one workgroup
-    // Hot vertices sit at ids 32r (r < 32 * hot_words): bit 0 of visited word r.
-    // hot_vis is their compact visited bitmap (bit r), which the restore pass
-    // keeps exact and expansion workgroups copy into LDS.
+    // The 32 * hot_words hot vertices sit at bit positions k << hot_shift of
+    // the first hot_span visited words (one per word with shift 5, bits 0 and
+    // 16 with shift 4). hot_vis is their compact visited bitmap (slot
+    // w + k * hot_span for position k of word w), which the restore pass keeps
+    // exact and expansion workgroups copy into LDS.
     uint32_t* hot_vis;
     uint32_t* hot_fr;          // compact bitmap of the hot vertices in the frontier (exact per level)
     int32_t hot_words;         // words of hot_vis / hot_fr (0 = off)
+    int32_t hot_shift;         // 5 or 4
+    int32_t hot_span;          // visited words holding hot vertices: hot_words << hot_shift
     int64_t hot_min_frontier;  // use an LDS copy only for frontiers of at least this many vertices
     // Without the degree-ordered copy: words of the visited bitmap (bottom-up
     // levels: of the frontier bitmap) that workgroups copy whole into LDS (0 = off).
@@ -202,28 +206,35 @@ __device__ __forceinline__ void record(const SingleParams& p, int32_t v, int lvl
     }
 }
 
+// Compact-bitmap slot of v if v is hot: position k = (v & 31) >> shift of
+// visited word w = v >> 5 < span has slot w + k * span.
+__device__ __forceinline__ bool hot_slot(uint32_t v, uint32_t span, uint32_t shift, uint32_t& slot) {
+    const uint32_t w = v >> 5;
+    slot = w + ((v & 31u) >> shift) * span;
+    return (v & ((1u << shift) - 1u)) == 0 && w < span;
+}
+
 // A workgroup's LDS copy of visited bits, taken at the start of a level (so a
-// set bit is final): either the compact bits of the hot ids 32r, r <
-// hot_limit (bit r), or the first full_words words of the visited bitmap
-// itself (bit v). Neither when both limits are 0.
+// set bit is final): either the compact bits of the hot ids (hot_span > 0),
+// or the first full_words words of the visited bitmap itself (bit v).
+// Neither when both are 0.
 struct LdsVis {
     uint32_t* bits;
-    uint32_t hot_limit;
+    uint32_t hot_span;
+    uint32_t hot_shift;
     uint32_t full_words;
 };
 
 // Bit of vertex v in the LDS copy, if the copy holds it.
 __device__ __forceinline__ bool lds_slot(const LdsVis& l, int32_t v, uint32_t& bit) {
-    const uint32_t r = (uint32_t)v >> 5;
     if (l.full_words) {
         bit = (uint32_t)v;
-        return r < l.full_words;
+        return ((uint32_t)v >> 5) < l.full_words;
     }
-    bit = r;
-    return (v & 31) == 0 && r < l.hot_limit;
+    return hot_slot((uint32_t)v, l.hot_span, l.hot_shift, bit);
 }
 
-// Hot ids (32r with r < hot_limit) are first looked up in the workgroup's LDS
+// Hot ids are first looked up in the workgroup's LDS
 // copy of the compact hot bitmap (taken at the start of the level, so a set bit
 // is final); only the rest, and hot ids not yet visited, probe the global bitmap.
 template <bool kAtomic, int U>
@@ -239,7 +250,7 @@ __device__ __forceinline__ void visit_arcs(const SingleParams& p, const int64_t 
     uint32_t w[U];
     bool in_lds[U];
     uint32_t slot[U];
-    const bool lds_on = (lds.hot_limit | lds.full_words) != 0;  // the same for the whole workgroup
+    const bool lds_on = (lds.hot_span | lds.full_words) != 0;  // the same for the whole workgroup
 #pragma unroll
     for (int i = 0; i < U; ++i) {
         in_lds[i] = ok[i] && lds_slot(lds, v[i], slot[i]);
@@ -728,9 +739,10 @@ __global__ __launch_bounds__(BLOCK) void k_init(SingleParams p, int nslots) {
         p.arcs_slot[i] = 0;
         p.reached_slot[i] = 0;
     }
-    const bool root_hot = (p.root & 31) == 0 && rw < (int64_t)p.hot_words * 32;
+    uint32_t rs = 0;
+    const bool root_hot = p.hot_words > 0 && hot_slot((uint32_t)p.root, (uint32_t)p.hot_span, (uint32_t)p.hot_shift, rs);
     for (int64_t i = gtid; i < p.hot_words; i += gsize) {
-        const uint32_t x = (root_hot && i == (rw >> 5)) ? 1u << (rw & 31) : 0u;
+        const uint32_t x = (root_hot && i == (rs >> 5)) ? 1u << (rs & 31) : 0u;
         p.hot_vis[i] = x;
         p.hot_fr[i] = x;
     }
@@ -850,7 +862,7 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl_arg) {
             // LDS copy of the frontier's hot bits, and whether the frontier has
             // any vertex outside the hot set.
             extern __shared__ uint32_t hot_lds[];
-            LdsVis lds{hot_lds, 0u, 0u};
+            LdsVis lds{hot_lds, 0u, 0u, 0u};
             bool cold_empty = false;
             if (p.hot_words > 0) {
                 const unsigned long long* src = reinterpret_cast<const unsigned long long*>(p.hot_fr);
@@ -867,7 +879,8 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl_arg) {
                 unsigned long long hot_in = 0;
                 for (int i = 0; i < NW; ++i) hot_in += sh.red[i];
                 cold_empty = hot_in == sh.found;
-                lds.hot_limit = (uint32_t)p.hot_words * 32u;
+                lds.hot_span = (uint32_t)p.hot_span;
+                lds.hot_shift = (uint32_t)p.hot_shift;
                 __syncthreads();
             } else if (p.full_words > 0) {
                 // The whole frontier bitmap.
@@ -885,12 +898,13 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl_arg) {
     // ---- LDS copy of visited bits (exact at level start): the compact hot
     // bitmap on the degree-ordered copy, else the whole visited snapshot
     extern __shared__ uint32_t hot_lds[];
-    LdsVis lds{hot_lds, 0u, 0u};
+    LdsVis lds{hot_lds, 0u, 0u, 0u};
     if (p.hot_words > 0 && (int64_t)sh.found >= p.hot_min_frontier) {
         const unsigned long long* src = reinterpret_cast<const unsigned long long*>(p.hot_vis);
         unsigned long long* dst = reinterpret_cast<unsigned long long*>(hot_lds);
         for (int i = tid; i < p.hot_words / 2; i += BLOCK) dst[i] = ld(src + i);
-        lds.hot_limit = (uint32_t)p.hot_words * 32u;
+        lds.hot_span = (uint32_t)p.hot_span;
+        lds.hot_shift = (uint32_t)p.hot_shift;
         __syncthreads();
     } else if (p.full_words > 0 && (int64_t)sh.found >= p.hot_min_frontier) {
         const unsigned long long* src = reinterpret_cast<const unsigned long long*>(p.vis_prev);
@@ -1028,17 +1042,22 @@ __global__ __launch_bounds__(kRestoreBlock) void k_restore(SingleParams p, int l
             if (cur != nv) st(p.vis + w, nv);
             st(p.vis_prev + w, nv);
         }
-        // Hot vertex of word w (id 32w) found this level: one compact word per
-        // half-wavefront, written by its first lane only.
-        if (p.hot_words > 0 && c * BLOCK < (int64_t)p.hot_words * 32) {
-            const uint64_t hm = __ballot(w < (int64_t)p.hot_words * 32 && (exact & 1u));
+        // Hot vertices of word w found this level: per hot bit position k,
+        // one compact word per half-wavefront (slots w + k * span of its 32
+        // words; span is a multiple of 32), written by its first lane only.
+        if (p.hot_words > 0 && c * BLOCK < p.hot_span) {
             const int half = lane >> 5;
-            const uint32_t bits = (uint32_t)(hm >> (32 * half));
-            if ((lane & 31) == 0 && bits) {
-                uint32_t* hw = p.hot_vis + (w >> 5);
-                st(hw, ld(hw) | bits);
+            const bool in = w < p.hot_span;
+            for (int k = 0; k < (32 >> p.hot_shift); ++k) {
+                const uint64_t hm = __ballot(in && ((exact >> (k << p.hot_shift)) & 1u));
+                const uint32_t bits = (uint32_t)(hm >> (32 * half));
+                const int64_t cw = (w >> 5) + (int64_t)k * (p.hot_span >> 5);
+                if ((lane & 31) == 0 && bits) {
+                    uint32_t* hw = p.hot_vis + cw;
+                    st(hw, ld(hw) | bits);
+                }
+                if ((lane & 31) == 0 && in) st(p.hot_fr + cw, bits);
             }
-            if ((lane & 31) == 0 && w < (int64_t)p.hot_words * 32) st(p.hot_fr + (w >> 5), bits);
         }
         if (w < p.words) {
             st(p.fr + w, exact);
@@ -1256,8 +1275,9 @@ __global__ __launch_bounds__(kSmallBlock) void k_small(SingleParams p) {
         for (uint32_t i = tid; i < nn; i += B) {
             const int32_t v = nxt[i];
             atomicOr(p.vis_prev + ((uint32_t)v >> 5), 1u << (v & 31));
-            const uint32_t r = (uint32_t)v >> 5;
-            if ((v & 31) == 0 && r < (uint32_t)p.hot_words * 32u) atomicOr(p.hot_vis + (r >> 5), 1u << (r & 31));
+            uint32_t r;
+            if (p.hot_words > 0 && hot_slot((uint32_t)v, (uint32_t)p.hot_span, (uint32_t)p.hot_shift, r))
+                atomicOr(p.hot_vis + (r >> 5), 1u << (r & 31));
         }
         if (tid == 0) {
             reached_done += nn;
@@ -1347,7 +1367,8 @@ __global__ void k_symmetry(const OffT* off, const int32_t* col, int64_t n, unsig
 // every neighbour renamed; one wavefront per row, arcs in their original order.
 template <typename OffT>
 __global__ void k_relabel_cols(const OffT* off, const int32_t* col, const int64_t* noff, const int32_t* new2old,
-                               const int32_t* old2new, int32_t* ncol, int64_t n, int32_t hot) {
+                               const int32_t* old2new, int32_t* ncol, int64_t n, int32_t hot_span,
+                               int32_t hot_shift) {
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -1358,9 +1379,10 @@ __global__ void k_relabel_cols(const OffT* off, const int32_t* col, const int64_
             // Short row: one sort across the wavefront. Hot neighbours first by
             // rank (highest degree first), then the others in arc order.
             const int32_t v = lane < d ? old2new[col[b + lane]] : -1;
-            const bool is_hot = v >= 0 && (v & 31) == 0 && (v >> 5) < hot;
+            uint32_t rank = 0;
+            const bool is_hot = v >= 0 && hot_slot((uint32_t)v, (uint32_t)hot_span, (uint32_t)hot_shift, rank);
             unsigned long long key = v < 0 ? ~0ull
-                                           : (is_hot ? (unsigned long long)(uint32_t)v
+                                           : (is_hot ? (unsigned long long)rank
                                                      : (1ull << 40) | (unsigned long long)lane);
             int32_t val = v;
             for (int k = 2; k <= 64; k <<= 1) {
@@ -1380,13 +1402,14 @@ __global__ void k_relabel_cols(const OffT* off, const int32_t* col, const int64_
             if (lane < d) ncol[nb + lane] = val;
             continue;
         }
-        // Long row: two stable passes, hot neighbours (ids 32r, r < hot) first, then the rest.
+        // Long row: two stable passes, hot neighbours first, then the rest.
         int64_t at = 0;
         for (int pass = 0; pass < 2; ++pass) {
             for (int64_t j0 = 0; j0 < d; j0 += 64) {
                 const int64_t j = j0 + lane;
                 const int32_t v = j < d ? old2new[col[b + j]] : -1;
-                const bool is_hot = v >= 0 && (v & 31) == 0 && (v >> 5) < hot;
+                uint32_t rank = 0;
+                const bool is_hot = v >= 0 && hot_slot((uint32_t)v, (uint32_t)hot_span, (uint32_t)hot_shift, rank);
                 const bool take = v >= 0 && (pass == 0 ? is_hot : !is_hot);
                 const uint64_t m = __ballot(take);
                 if (take) ncol[nb + at + rank_in(m)] = v;
@@ -1550,13 +1573,18 @@ void launch_single(bfs_graph* g, const bfs_tunables& t, Workspace* w, int32_t ro
     p.t1 = t.small_max_degree;
     p.min_share = t.chunk_arcs > 0 ? t.chunk_arcs : 1024;
     p.hot_words = h ? h->hot / 32 : 0;
+    p.hot_shift = h ? h->shift : 5;
+    p.hot_span = h ? h->span : 0;
     p.hot_vis = w->hot_vis;
     p.hot_fr = w->hot_fr;
     p.hot_min_frontier = std::max<int64_t>(4096, g->n / 256);
     p.full_words = (int32_t)lds_visited_words(g, t);
     if (p.full_words % 64 != 0 || p.full_words > w->words) fail(BFS_E_INTERNAL, "LDS visited words out of range");
-    if ((int64_t)p.hot_words * 32 > w->words || p.hot_words % 2 != 0 || p.hot_words > w->hot_capacity)
+    if ((int64_t)p.hot_words * 32 > w->words * 2 || p.hot_words % 2 != 0 || p.hot_words > w->hot_capacity)
         fail(BFS_E_INTERNAL, "hot bitmap larger than its buffer");
+    if (h && (h->hot % 64 != 0 || (h->shift != 5 && h->shift != 4) || h->span != (h->hot / 32) << h->shift ||
+              h->span % 32 != 0 || (int64_t)h->span * 32 > g->n))
+        fail(BFS_E_INTERNAL, "hot layout out of range");
     if (w->big_capacity < bt.num_big) fail(BFS_E_INTERNAL, "big-row list too small");
     if (hybrid && !g->symmetric) fail(BFS_E_INVALID_ARG, "bottom-up levels need a graph loaded as symmetric");
     p.nnz = g->nnz;
@@ -1655,14 +1683,14 @@ bool csr_is_symmetric(const bfs_graph* g) {
 }
 
 void launch_relabel_cols(const bfs_graph* g, const int64_t* d_noff, const int32_t* d_new2old,
-                         const int32_t* d_old2new, int32_t* d_ncol, int32_t hot) {
+                         const int32_t* d_old2new, int32_t* d_ncol, int32_t hot_span, int32_t hot_shift) {
     const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((g->n + 3) / 4, (int64_t)g->cu_count * 32));
     if (g->off32)
         k_relabel_cols<int32_t><<<blocks, 256>>>(static_cast<const int32_t*>(g->d_off), g->d_col, d_noff, d_new2old,
-                                                 d_old2new, d_ncol, g->n, hot);
+                                                 d_old2new, d_ncol, g->n, hot_span, hot_shift);
     else
         k_relabel_cols<int64_t><<<blocks, 256>>>(static_cast<const int64_t*>(g->d_off), g->d_col, d_noff, d_new2old,
-                                                 d_old2new, d_ncol, g->n, hot);
+                                                 d_old2new, d_ncol, g->n, hot_span, hot_shift);
     BFS_HIP(hipGetLastError());
 }
 

@@ -41,6 +41,7 @@ def test_hybrid_erdos_renyi_and_int32_offsets():
 
 
 @pytest.mark.parametrize("tun", [dict(update_mode=2), dict(hot_vertices=8192, block_size=1024),
+                                 dict(hot_vertices=16384, block_size=1024),
                                  dict(small_max_degree=1, wave_max_degree=1),
                                  dict(lds_visited=1, block_size=1024), dict(lds_visited=-1)])
 def test_hybrid_tunables(tun):

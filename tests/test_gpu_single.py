@@ -99,7 +99,8 @@ def test_device_pointer_graph():
     dict(block_size=256, blocks_per_cu=2, update_mode=2),
     dict(block_size=512, blocks_per_cu=1, update_mode=1),
     dict(block_size=1024, blocks_per_cu=1),
-    dict(hot_vertices=2048),                                    # LDS hot bitmap at every large level
+    dict(hot_vertices=512),                                     # LDS hot bitmap, one hot vertex per visited word
+    dict(hot_vertices=2048),                                    # capped at 1024: two per word (bits 0 and 16)
     dict(hot_vertices=2048, update_mode=2),
     dict(hot_vertices=65536, block_size=1024, small_max_degree=256),
     dict(lds_visited=1, block_size=1024),                       # whole visited bitmap in LDS
@@ -201,6 +202,7 @@ def test_rmat_scale20_64_roots():
 
 
 @pytest.mark.parametrize("tun", [dict(hot_vertices=8192, block_size=1024), dict(hot_vertices=8192, update_mode=2),
+                                 dict(hot_vertices=16384, block_size=1024), dict(hot_vertices=16384, update_mode=2),
                                  dict(lds_visited=1, block_size=1024), dict(lds_visited=-1)])
 def test_hot_bitmap_scale18(tun):
     """The LDS copy of the hot bitmap changes probes only, never results: levels

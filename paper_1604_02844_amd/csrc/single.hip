@@ -215,23 +215,43 @@ __device__ __forceinline__ bool hot_slot(uint32_t v, uint32_t span, uint32_t shi
 }
 
 // A workgroup's LDS copy of visited bits, taken at the start of a level (so a
-// set bit is final): either the compact bits of the hot ids (hot_span > 0),
-// or the first full_words words of the visited bitmap itself (bit v).
-// Neither when both are 0.
+// set bit is final): either the compact bits of the hot ids, or the first
+// words of the visited bitmap itself (bit v). One form covers both, so a
+// lookup needs no branch: v is held if v & mask == 0 and its word w = v >> 5
+// is below lim, at bit (w << wshift) + ((v & 31) >> shift) * kmul.
+//   hot bits:  mask 2^hot_shift - 1, lim hot_span, shift hot_shift, wshift 0, kmul hot_span;
+//   whole words: mask 0, lim full_words, shift 0, wshift 5, kmul 1;
+//   no copy: lim 0.
 struct LdsVis {
     uint32_t* bits;
-    uint32_t hot_span;
-    uint32_t hot_shift;
-    uint32_t full_words;
+    uint32_t lim;
+    uint32_t mask;
+    uint32_t shift;
+    uint32_t wshift;
+    uint32_t kmul;
+
+    __device__ static LdsVis none(uint32_t* b) { return LdsVis{b, 0u, 0u, 0u, 0u, 0u}; }
+    __device__ void set_hot(uint32_t span, uint32_t hshift) {
+        lim = span;
+        mask = (1u << hshift) - 1u;
+        shift = hshift;
+        wshift = 0u;
+        kmul = span;
+    }
+    __device__ void set_words(uint32_t words) {
+        lim = words;
+        mask = 0u;
+        shift = 0u;
+        wshift = 5u;
+        kmul = 1u;
+    }
 };
 
 // Bit of vertex v in the LDS copy, if the copy holds it.
 __device__ __forceinline__ bool lds_slot(const LdsVis& l, int32_t v, uint32_t& bit) {
-    if (l.full_words) {
-        bit = (uint32_t)v;
-        return ((uint32_t)v >> 5) < l.full_words;
-    }
-    return hot_slot((uint32_t)v, l.hot_span, l.hot_shift, bit);
+    const uint32_t u = (uint32_t)v, w = u >> 5;
+    bit = (w << l.wshift) + __umul24((u & 31u) >> l.shift, l.kmul);  // both factors below 2^24
+    return ((u & l.mask) == 0u) & (w < l.lim);
 }
 
 // Hot ids are first looked up in the workgroup's LDS
@@ -249,14 +269,20 @@ __device__ __forceinline__ void visit_arcs(const SingleParams& p, const int64_t 
     for (int i = 0; i < U; ++i) v[i] = __builtin_nontemporal_load(p.col + pos[i]);
     uint32_t w[U];
     bool in_lds[U];
-    uint32_t slot[U];
-    const bool lds_on = (lds.hot_span | lds.full_words) != 0;  // the same for the whole workgroup
+    uint32_t slot[U], lw[U];
+#pragma unroll
+    for (int i = 0; i < U; ++i) in_lds[i] = ok[i] & lds_slot(lds, v[i], slot[i]);
+    if (lds.lim != 0) {  // the same for the whole workgroup
+#pragma unroll
+        for (int i = 0; i < U; ++i) lw[i] = lds.bits[in_lds[i] ? slot[i] >> 5 : 0];
+    } else {
+#pragma unroll
+        for (int i = 0; i < U; ++i) lw[i] = 0u;
+    }
 #pragma unroll
     for (int i = 0; i < U; ++i) {
-        in_lds[i] = ok[i] && lds_slot(lds, v[i], slot[i]);
-        const uint32_t lw = lds_on ? lds.bits[in_lds[i] ? slot[i] >> 5 : 0] : 0u;
-        const bool known = in_lds[i] && ((lw >> (slot[i] & 31)) & 1u);
-        const bool need = ok[i] && !known;
+        const bool known = in_lds[i] & (((lw[i] >> (slot[i] & 31)) & 1u) != 0u);
+        const bool need = ok[i] & !known;
         const uint32_t x = p.vis[need ? (uint32_t)v[i] >> 5 : 0u];
         w[i] = need ? x : ~0u;
     }
@@ -862,7 +888,7 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl_arg) {
             // LDS copy of the frontier's hot bits, and whether the frontier has
             // any vertex outside the hot set.
             extern __shared__ uint32_t hot_lds[];
-            LdsVis lds{hot_lds, 0u, 0u, 0u};
+            LdsVis lds = LdsVis::none(hot_lds);
             bool cold_empty = false;
             if (p.hot_words > 0) {
                 const unsigned long long* src = reinterpret_cast<const unsigned long long*>(p.hot_fr);
@@ -879,15 +905,14 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl_arg) {
                 unsigned long long hot_in = 0;
                 for (int i = 0; i < NW; ++i) hot_in += sh.red[i];
                 cold_empty = hot_in == sh.found;
-                lds.hot_span = (uint32_t)p.hot_span;
-                lds.hot_shift = (uint32_t)p.hot_shift;
+                lds.set_hot((uint32_t)p.hot_span, (uint32_t)p.hot_shift);
                 __syncthreads();
             } else if (p.full_words > 0) {
                 // The whole frontier bitmap.
                 const unsigned long long* src = reinterpret_cast<const unsigned long long*>(p.fr);
                 unsigned long long* dst = reinterpret_cast<unsigned long long*>(hot_lds);
                 for (int i = tid; i < p.full_words / 2; i += BLOCK) dst[i] = ld(src + i);
-                lds.full_words = (uint32_t)p.full_words;
+                lds.set_words((uint32_t)p.full_words);
                 __syncthreads();
             }
             bottom_up<OffT, BLOCK>(p, sh, lvl, lds, cold_empty);
@@ -898,19 +923,18 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl_arg) {
     // ---- LDS copy of visited bits (exact at level start): the compact hot
     // bitmap on the degree-ordered copy, else the whole visited snapshot
     extern __shared__ uint32_t hot_lds[];
-    LdsVis lds{hot_lds, 0u, 0u, 0u};
+    LdsVis lds = LdsVis::none(hot_lds);
     if (p.hot_words > 0 && (int64_t)sh.found >= p.hot_min_frontier) {
         const unsigned long long* src = reinterpret_cast<const unsigned long long*>(p.hot_vis);
         unsigned long long* dst = reinterpret_cast<unsigned long long*>(hot_lds);
         for (int i = tid; i < p.hot_words / 2; i += BLOCK) dst[i] = ld(src + i);
-        lds.hot_span = (uint32_t)p.hot_span;
-        lds.hot_shift = (uint32_t)p.hot_shift;
+        lds.set_hot((uint32_t)p.hot_span, (uint32_t)p.hot_shift);
         __syncthreads();
     } else if (p.full_words > 0 && (int64_t)sh.found >= p.hot_min_frontier) {
         const unsigned long long* src = reinterpret_cast<const unsigned long long*>(p.vis_prev);
         unsigned long long* dst = reinterpret_cast<unsigned long long*>(hot_lds);
         for (int i = tid; i < p.full_words / 2; i += BLOCK) dst[i] = ld(src + i);
-        lds.full_words = (uint32_t)p.full_words;
+        lds.set_words((uint32_t)p.full_words);
         __syncthreads();
     }
 

@@ -244,3 +244,23 @@ def test_small_level_kernel_shapes(sparse):
         dg = load(g)
         bfs.bfs_graph_set_tunables(dg, sparse_frontier=sparse)
         check_root(g, dg, r)
+
+
+@pytest.mark.parametrize("hot", [1500, 4096, 100000])
+@pytest.mark.parametrize("flags", [0, bfs.BFS_HYBRID])
+def test_hot_layout_ragged_vertex_count(hot, flags):
+    """Hot sets on a skewed graph whose vertex count is not a multiple of 32
+    (n = 50,001, 1562 full visited words): 1500 rounds up to 1536, one hot
+    vertex per word; 4096 is capped at 3072, two per word (bits 0 and 16);
+    100000 is capped the same way. Levels exact, parents valid, top-down and
+    direction-optimising."""
+    n = 50_001
+    src, dst = graphgen.rmat_edges(16, 16 << 16, seed=61)
+    g = graphgen.from_edges(n, (src % n).tolist(), (dst % n).tolist())
+    dg = load(g, symmetric=True)
+    bfs.bfs_graph_set_tunables(dg, hot_vertices=hot, block_size=1024)
+    deg = np.diff(g.offsets)
+    roots = [int(np.argmax(deg)), int(n - 1) if deg[n - 1] > 0 else int(np.flatnonzero(deg)[-1])]
+    roots += [int(r) for r in graphgen.pick_roots(g, 2, seed=62)]
+    for r in roots:
+        check_root(g, dg, r, flags=flags)

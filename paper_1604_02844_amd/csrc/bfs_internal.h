@@ -160,7 +160,8 @@ struct HotLayout {
     int32_t span = 0;   // visited words holding hot vertices
     int64_t* d_off = nullptr;       // [n+1], new order
     int32_t* d_col = nullptr;       // [nnz], new ids
-    int32_t* d_new2old = nullptr;   // [n]
+    int32_t* d_new2old = nullptr;   // [n] run id -> caller id
+    int32_t* d_old2new = nullptr;   // [n] caller id -> run id
     std::vector<int32_t> old2new;   // host copy, for the root
     BigTable big;
     int64_t bytes = 0;

@@ -153,6 +153,7 @@ void free_hot_layout(bfs_graph* g) {
     if (h.d_off) (void)hipFree(h.d_off);
     if (h.d_col) (void)hipFree(h.d_col);
     if (h.d_new2old) (void)hipFree(h.d_new2old);
+    if (h.d_old2new) (void)hipFree(h.d_old2new);
     free_big_table(h.big);
     g->device_bytes -= h.bytes;
     g->hot.reset();
@@ -217,31 +218,28 @@ void build_hot_layout(bfs_graph* g, int32_t hot, int32_t threshold) {
     h->hot = hot;
     h->shift = shift;
     h->span = (int32_t)span;
-    int32_t* d_old2new = nullptr;
     try {
         BFS_HIP(hipMalloc(&h->d_off, noff.size() * 8));
         BFS_HIP(hipMalloc(&h->d_col, std::max<size_t>((size_t)g->nnz * 4, 4)));
         BFS_HIP(hipMalloc(&h->d_new2old, (size_t)n * 4));
-        BFS_HIP(hipMalloc(&d_old2new, (size_t)n * 4));
+        BFS_HIP(hipMalloc(&h->d_old2new, (size_t)n * 4));
         BFS_HIP(hipMemcpy(h->d_off, noff.data(), noff.size() * 8, hipMemcpyHostToDevice));
         BFS_HIP(hipMemcpy(h->d_new2old, new2old.data(), (size_t)n * 4, hipMemcpyHostToDevice));
-        BFS_HIP(hipMemcpy(d_old2new, old2new.data(), (size_t)n * 4, hipMemcpyHostToDevice));
-        launch_relabel_cols(g, h->d_off, h->d_new2old, d_old2new, h->d_col, h->span, h->shift);
+        BFS_HIP(hipMemcpy(h->d_old2new, old2new.data(), (size_t)n * 4, hipMemcpyHostToDevice));
+        launch_relabel_cols(g, h->d_off, h->d_new2old, h->d_old2new, h->d_col, h->span, h->shift);
         BFS_HIP(hipDeviceSynchronize());
-        BFS_HIP(hipFree(d_old2new));
-        d_old2new = nullptr;
         build_big_table(h->big, h->d_off, false, n, threshold, g->restore_grid, g->cu_count, nullptr);
         if (h->big.num_big != g->big.num_big) fail(BFS_E_INTERNAL, "degree-ordered copy changed the big rows");
     } catch (...) {
-        if (d_old2new) (void)hipFree(d_old2new);
         if (h->d_off) (void)hipFree(h->d_off);
         if (h->d_col) (void)hipFree(h->d_col);
         if (h->d_new2old) (void)hipFree(h->d_new2old);
+        if (h->d_old2new) (void)hipFree(h->d_old2new);
         free_big_table(h->big);
         throw;
     }
     h->old2new = std::move(old2new);
-    h->bytes = (int64_t)noff.size() * 8 + g->nnz * 4 + n * 4 + h->big.bytes;
+    h->bytes = (int64_t)noff.size() * 8 + g->nnz * 4 + n * 8 + h->big.bytes;
     g->device_bytes += h->bytes;
     g->hot = std::move(h);
 }

@@ -73,6 +73,7 @@ struct SingleParams {
     int32_t* out_lv;           // the caller's levels and parents, by caller ids
     int32_t* out_pa;
     const int32_t* new2old;    // run id -> caller id on the degree-ordered copy, else nullptr
+    const int32_t* old2new;    // caller id -> run id on the degree-ordered copy, else nullptr
     int32_t root_out;          // the root as a caller id
     uint32_t* vis;
     uint32_t* vis_prev;
@@ -812,16 +813,17 @@ __global__ __launch_bounds__(BLOCK) void k_init(SingleParams p, int nslots) {
 }
 
 // After the last level on the degree-ordered copy: the caller's levels and
-// parents from the run's records, in run order (reads coalesced; cold ids keep
-// the caller's order, so the writes are nearly coalesced too).
-__global__ __launch_bounds__(256) void k_out(const int2* rec, const int32_t* new2old, int32_t* out_lv,
+// parents from the run's records, in caller order. The writes are coalesced;
+// cold ids keep the caller's order, so the record reads are nearly coalesced
+// too, and only the hot vertices' records are gathered one by one (a random
+// read costs one line, a random partial-line write a fetch and a write-back).
+__global__ __launch_bounds__(256) void k_out(const unsigned long long* rec, const int32_t* old2new, int32_t* out_lv,
                                              int32_t* out_pa, int64_t n) {
     const int64_t gsize = (int64_t)gridDim.x * 256;
-    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < n; v += gsize) {
-        const int2 r = rec[v];
-        const int32_t o = new2old[v];
-        out_lv[o] = r.x;
-        out_pa[o] = r.y;
+    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < n; c += gsize) {
+        const unsigned long long r = ld(rec + old2new[c]);  // {level, parent}, written by earlier launches
+        out_lv[c] = (int32_t)(uint32_t)r;
+        out_pa[c] = (int32_t)(uint32_t)(r >> 32);
     }
 }
 
@@ -1542,7 +1544,8 @@ void launch_typed(bfs_graph* g, const bfs_tunables& t, Workspace* w, SingleParam
     if (w->host_ctrl->done) w->last_launches = small ? w->host_ctrl->steps : w->host_ctrl->num_levels + 1;
     if (p.new2old) {
         const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((p.n + 255) / 256, (int64_t)g->cu_count * 16));
-        k_out<<<blocks, 256, 0, s>>>(reinterpret_cast<const int2*>(p.lv), p.new2old, p.out_lv, p.out_pa, p.n);
+        k_out<<<blocks, 256, 0, s>>>(reinterpret_cast<const unsigned long long*>(p.lv), p.old2new, p.out_lv,
+                                     p.out_pa, p.n);
         BFS_HIP(hipGetLastError());
     }
 }
@@ -1580,6 +1583,7 @@ void launch_single(bfs_graph* g, const bfs_tunables& t, Workspace* w, int32_t ro
     p.out_lv = levels;
     p.out_pa = parents;
     p.new2old = h ? h->d_new2old : nullptr;
+    p.old2new = h ? h->d_old2new : nullptr;
     p.vis = w->vis;
     p.vis_prev = w->vis_prev;
     p.fr = w->fr;

@@ -62,6 +62,7 @@ def parse():
     ap.add_argument("--rates", default="1000,5000,10000,20000,50000", help="serve: arrival rates (queries/s)")
     ap.add_argument("--queries", type=int, default=4000, help="serve: queries per rate")
     ap.add_argument("--warmup-queries", type=int, default=400, help="serve: leading queries left out of the stats")
+    ap.add_argument("--server-config", default="", help='serve: JSON object of bfs_server_create arguments, e.g. {"num_streams": 8}')
     return ap.parse_args()
 
 
@@ -330,7 +331,7 @@ def bench_serve(args) -> int:
     for rate in rates:
         arrivals, choice, roots = _trace(graphs, rate, args.queries, 3)
         # --- continuous-batching server
-        srv = bfs.bfs_server_create()
+        srv = bfs.bfs_server_create(**(json.loads(args.server_config) if args.server_config else {}))
         gids = [bfs.bfs_server_add_graph(srv, d) for d in dgs]
         tickets = [None] * args.queries
         done = {}
@@ -405,7 +406,8 @@ def bench_serve(args) -> int:
            "unit": "GTEPS", "n_gpus": 1, "higher_is_better": True, "dtype": "int32", "data": "synthetic",
            "config": {"workload": "8 resident graphs (R-MAT 16/18/20/22/24, ER 2^18 d8, 2^20 d16, 2^22 d32), "
                                   "Poisson arrivals, Zipf(1.1) graph choice, uniform roots of degree>0",
-                      "warmup_queries": args.warmup_queries},
+                      "warmup_queries": args.warmup_queries,
+                      "server_config": json.loads(args.server_config) if args.server_config else {}},
            "rates": per_rate}
     print(json.dumps(out), flush=True)
     return 0

@@ -216,8 +216,8 @@ int bfs_autotune(bfs_graph* g, const int32_t* roots, int32_t num_roots, int32_t 
 typedef struct {
     int64_t mem_budget_bytes;       /* device bytes for instances and results; 0 = 50% of free */
     int32_t max_slots;              /* roots per multi-source instance (1..64); 0 = 64 */
-    int32_t num_streams;            /* HIP streams shared by instances; 0 = 4 */
-    int32_t max_instances_per_graph;/* concurrent instances of one graph; 0 = 2 */
+    int32_t num_streams;            /* HIP streams shared by instances; 0 = 16 */
+    int32_t max_instances_per_graph;/* concurrent instances of one graph; 0 = 3 */
     int32_t flags;                  /* reserved, must be 0 */
     int32_t single_workers;         /* threads that serve lightly loaded graphs with single-root
                                        runs (bfs_run), each on its own stream; 0 or -1 = none:

@@ -319,7 +319,10 @@ void scheduler(bfs_server* s) {
             }
             if (!busy && !running && !s->stop) s->cv.wait_for(lk, std::chrono::milliseconds(2));
             if (s->stop) return;
-            if (s->fatal) continue;
+            if (s->fatal) {  // nothing runs any more: wait for bfs_server_destroy
+                s->cv.wait_for(lk, std::chrono::milliseconds(2));
+                continue;
+            }
             try {
                 admit(s);
             } catch (const bfs::Error& e) {

@@ -431,6 +431,7 @@ struct ExpandShared {
     unsigned long long big_total;
     unsigned long long seen;  // hybrid runs: vertices visited before this frontier
     int was_bu;               // hybrid runs: the previous level ran bottom-up
+    int done;                 // the run had already ended
     int64_t staged_end;  // last arc (exclusive) of the staged big rows
     uint32_t row0;
 };
@@ -834,33 +835,48 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl_arg) {
     __shared__ ExpandShared<BLOCK> sh;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int64_t G = gridDim.x, bid = blockIdx.x;
-    if (ld(&p.ctrl->done)) return;
     // With the small-level kernel on (lvl_arg < 0) the level lives in the
     // control block, and that kernel may have expanded it already.
-    if (lvl_arg < 0 && ld(&p.ctrl->skip_e)) return;
-    const int lvl = lvl_arg >= 0 ? lvl_arg : ld(&p.ctrl->level);
+    int lvl = lvl_arg;
+    if (lvl_arg < 0) {
+        if (ld(&p.ctrl->done)) return;
+        if (ld(&p.ctrl->skip_e)) return;
+        lvl = ld(&p.ctrl->level);
+    }
 
-    // Termination, and the arcs of the frontier's rows above T2: both counted
-    // by the previous restore, read in one round.
+    // Whether the run has ended, the frontier size and the arcs of the
+    // frontier's rows above T2 (both counted by the previous restore), and
+    // the direction state: all read in one round (small levels are bound by
+    // such round trips).
     if (tid < 64) {
+        int dn = 0, wb = 0;
+        unsigned long long sn = 0;
+        if (tid == 0) {
+            if (lvl_arg >= 0) dn = ld(&p.ctrl->done);
+            if (p.hybrid) {
+                wb = ld(&p.ctrl->dir[lvl & 1]);
+                sn = ld(&p.ctrl->visited[lvl & 1]);
+            }
+        }
         unsigned long long c = ld(stripe(p.ctrl, lvl & 1, tid));
         unsigned long long b = ld(&p.ctrl->bigarcs[lvl & 1][tid * kStripeStride]);
         c = wave_sum(c);
         b = wave_sum(b);
+        dn = __shfl(dn, 0, 64);
         if (tid == 0) {
+            sh.done = dn;
             sh.found = c;
             sh.big_total = b;
-            if (p.hybrid) {
-                sh.was_bu = ld(&p.ctrl->dir[lvl & 1]);
-                sh.seen = ld(&p.ctrl->visited[lvl & 1]);
-            }
+            sh.was_bu = wb;
+            sh.seen = sn;
         }
-        if (bid == 0) {  // counters for the next level
+        if (bid == 0 && !dn) {  // counters for the next level
             st(stripe(p.ctrl, (lvl + 1) & 1, tid), 0ull);
             st(&p.ctrl->bigarcs[(lvl + 1) & 1][tid * kStripeStride], 0ull);
         }
     }
     __syncthreads();
+    if (sh.done) return;
     if (sh.found == 0) {
         if (bid == 0 && tid == 0) {
             p.ctrl->num_levels = lvl;
@@ -1003,8 +1019,17 @@ __global__ __launch_bounds__(kRestoreBlock) void k_restore(SingleParams p, int l
     __shared__ unsigned long long red[BLOCK / 64];
     __shared__ uint32_t tmp[BLOCK / 64];
     __shared__ uint32_t listed;  // next-frontier ids of this block so far
-    if (ld(&p.ctrl->done)) return;
-    const int lvl = lvl_arg >= 0 ? lvl_arg : ld(&p.ctrl->level);
+    // Whether the run has ended and (hybrid runs) the direction of the level
+    // just expanded, read in one round where the level is known.
+    int lvl = lvl_arg, dir_bu = 0;
+    const int dn = ld(&p.ctrl->done);
+    if (lvl_arg >= 0) {
+        if (!kAtomic && p.hybrid) dir_bu = ld(&p.ctrl->dir[(lvl + 1) & 1]);
+    } else if (!dn) {
+        lvl = ld(&p.ctrl->level);
+        if (!kAtomic && p.hybrid) dir_bu = ld(&p.ctrl->dir[(lvl + 1) & 1]);
+    }
+    if (dn) return;
     const int tid = threadIdx.x;
     if (tid == 0) listed = 0;
     __syncthreads();
@@ -1015,7 +1040,7 @@ __global__ __launch_bounds__(kRestoreBlock) void k_restore(SingleParams p, int l
     const int32_t first = p.seg_start[bid];
     // A bottom-up level wrote every changed word once, from its owner, with
     // exactly the new bits: no lost updates to put back.
-    const bool exact_words = kAtomic || (p.hybrid && ld(&p.ctrl->dir[(lvl + 1) & 1]) != 0);
+    const bool exact_words = kAtomic || (p.hybrid && dir_bu != 0);
     for (int64_t c = bid; c * BLOCK < p.words; c += G) {
         const int64_t w = c * BLOCK + tid;
         const int lane = tid & 63;

@@ -999,14 +999,14 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl_arg) {
         process_batch<OffT, kAtomic>(p, u, valid, lane, lvl + 1, arcs, lds, sh.x.w.starts[wid]);
     }
 
-    // ---- block total of scanned arcs (plain update of this block's own slot)
+    // ---- block total of scanned arcs (added to this block's own slot)
     const unsigned long long asum = wave_sum(arcs);
     if (lane == 0) sh.red[wid] = asum;
     __syncthreads();
     if (tid == 0) {
         unsigned long long a = 0;
         for (int i = 0; i < NW; ++i) a += sh.red[i];
-        p.arcs_slot[bid] += a;
+        if (a) atomicAdd(p.arcs_slot + bid, a);  // no returned value: nothing to wait for
     }
 }
 
@@ -1044,10 +1044,11 @@ __global__ __launch_bounds__(kRestoreBlock) void k_restore(SingleParams p, int l
     for (int64_t c = bid; c * BLOCK < p.words; c += G) {
         const int64_t w = c * BLOCK + tid;
         const int lane = tid & 63;
-        uint32_t cur = 0, prev = 0, exact = 0;
+        uint32_t cur = 0, prev = 0, exact = 0, bm = 0;
         if (w < p.words) {
             cur = ld(p.vis + w);
             prev = ld(p.vis_prev + w);
+            bm = p.bigmap[w];  // read-only graph data, read in the same round
         }
         const bool touched = w < p.words && cur != prev;
         if (exact_words) {
@@ -1122,7 +1123,7 @@ __global__ __launch_bounds__(kRestoreBlock) void k_restore(SingleParams p, int l
                 st(p.sl + bid * kSmallSeg + at, (int32_t)(w * 32 + __builtin_ctz(x)));
         }
         // Append the next frontier's big rows of this chunk to the segment.
-        const uint32_t big = w < p.words ? (exact & p.bigmap[w]) : 0u;
+        const uint32_t big = exact & bm;
         uint32_t my_arcs = 0;
         for (uint32_t x = big; x; x &= x - 1) {
             const int64_t u = w * 32 + __builtin_ctz(x);
@@ -1153,7 +1154,7 @@ __global__ __launch_bounds__(kRestoreBlock) void k_restore(SingleParams p, int l
         for (int i = 0; i < BLOCK / 64; ++i) a += red[i];
         if (a) {
             atomicAdd(stripe(p.ctrl, next & 1, (int)(bid % kStripes)), a);
-            p.reached_slot[bid] += a;
+            atomicAdd(p.reached_slot + bid, a);
         }
         st(p.seg_cnt + bid, seg_n);
         st(p.seg_arcs + bid, seg_a);

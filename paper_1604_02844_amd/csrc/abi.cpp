@@ -154,9 +154,13 @@ int bfs_run(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents, void*
                 pa = w->out_parents;
             }
             BFS_HIP(hipEventRecord(w->ev_start, s));
-            bfs::launch_single(g, t, w, root, lv, pa, s, hybrid);
-            if (least_parents) bfs::launch_least_parents(g, lv, pa, s);
-            BFS_HIP(hipEventRecord(w->ev_stop, s));
+            if (least_parents) {
+                bfs::launch_single(g, t, w, root, lv, pa, s, hybrid);
+                bfs::launch_least_parents(g, lv, pa, s);
+                BFS_HIP(hipEventRecord(w->ev_stop, s));
+            } else {
+                bfs::launch_single(g, t, w, root, lv, pa, s, hybrid, w->ev_stop);
+            }
             if (host_out) {
                 BFS_HIP(hipMemcpyAsync(levels, lv, (size_t)g->n * 4, hipMemcpyDeviceToHost, s));
                 BFS_HIP(hipMemcpyAsync(parents, pa, (size_t)g->n * 4, hipMemcpyDeviceToHost, s));

@@ -240,8 +240,10 @@ void release_ms(bfs_graph* g, MsWorkspace* w, hipStream_t s);
 void free_workspaces(bfs_graph* g);
 
 // Launchers (the kernels live in single.hip and multi.hip).
+// stop (nullable) is recorded on s right after the run's last kernel, before
+// the host learns that the run has ended.
 void launch_single(bfs_graph* g, const bfs_tunables& t, Workspace* w, int32_t root, int32_t* levels,
-                   int32_t* parents, hipStream_t s, bool hybrid = false);
+                   int32_t* parents, hipStream_t s, bool hybrid = false, hipEvent_t stop = nullptr);
 void launch_single_stats(Workspace* w, hipStream_t s);
 // Stats of a run from its level array (hybrid runs scan no frontier rows in
 // bottom-up levels): reached and the sum of their degrees.

@@ -1535,7 +1535,8 @@ Grids grids_for(bfs_graph* g, const bfs_tunables& t, int64_t nslots, int lds_wor
 }
 
 template <typename OffT, int BLOCK, bool kAtomic>
-void launch_typed(bfs_graph* g, const bfs_tunables& t, Workspace* w, SingleParams& p, hipStream_t s) {
+void launch_typed(bfs_graph* g, const bfs_tunables& t, Workspace* w, SingleParams& p, hipStream_t s,
+                  hipEvent_t stop) {
     const int lds_words = std::max<int>(p.hot_words, p.full_words);
     const Grids gr = grids_for<OffT, BLOCK, kAtomic>(g, t, w->nslots, lds_words);
     const int init_grid = (int)std::min<int64_t>(std::max<int64_t>(p.n / 4, p.words) / BLOCK + 1, 4096);
@@ -1548,9 +1549,24 @@ void launch_typed(bfs_graph* g, const bfs_tunables& t, Workspace* w, SingleParam
     // steps as the previous run on this workspace used (runs from other roots
     // of one graph have similar shapes), so most runs end inside it.
     // Without the small-level kernel a step is one level, passed as an argument.
+    // When the previous run's step count says this chunk ends the run, the
+    // output pass and the stop event go in before the host waits, so the
+    // host's wake-up is not inside the timed span; if the run goes on, a later
+    // chunk repeats both.
     const bool small = p.s_max > 0;
+    const int64_t expect = w->last_launches;  // 0: unknown
     int64_t steps = 0;
     int chunk = std::max(4, std::min(64, w->last_launches + 1));
+    bool finished_early = false;
+    auto finish = [&] {
+        if (p.new2old) {
+            const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((p.n + 255) / 256, (int64_t)g->cu_count * 16));
+            k_out<<<blocks, 256, 0, s>>>(reinterpret_cast<const unsigned long long*>(p.lv), p.old2new, p.out_lv,
+                                         p.out_pa, p.n);
+            BFS_HIP(hipGetLastError());
+        }
+        if (stop) BFS_HIP(hipEventRecord(stop, s));
+    };
     while (true) {
         for (int i = 0; i < chunk; ++i) {
             const int lvl = small ? -1 : (int)(steps + i);
@@ -1560,6 +1576,8 @@ void launch_typed(bfs_graph* g, const bfs_tunables& t, Workspace* w, SingleParam
         }
         BFS_HIP(hipGetLastError());
         steps += chunk;
+        finished_early = expect > 0 && steps >= expect;
+        if (finished_early) finish();
         static_assert(offsetof(Ctrl, steps) == offsetof(Ctrl, done) + 3 * sizeof(int), "done .. steps");
         BFS_HIP(hipMemcpyAsync(&w->host_ctrl->done, &p.ctrl->done, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
         BFS_HIP(hipStreamSynchronize(s));
@@ -1568,12 +1586,7 @@ void launch_typed(bfs_graph* g, const bfs_tunables& t, Workspace* w, SingleParam
     }
     // The step that found the frontier empty was the last one with work.
     if (w->host_ctrl->done) w->last_launches = small ? w->host_ctrl->steps : w->host_ctrl->num_levels + 1;
-    if (p.new2old) {
-        const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((p.n + 255) / 256, (int64_t)g->cu_count * 16));
-        k_out<<<blocks, 256, 0, s>>>(reinterpret_cast<const unsigned long long*>(p.lv), p.old2new, p.out_lv,
-                                     p.out_pa, p.n);
-        BFS_HIP(hipGetLastError());
-    }
+    if (!finished_early) finish();
 }
 
 }  // namespace
@@ -1585,7 +1598,7 @@ int64_t lds_visited_words_max(int block) {
 }
 
 void launch_single(bfs_graph* g, const bfs_tunables& t, Workspace* w, int32_t root, int32_t* levels,
-                   int32_t* parents, hipStream_t s, bool hybrid) {
+                   int32_t* parents, hipStream_t s, bool hybrid, hipEvent_t stop) {
     // Host-side checks of what the kernels assume about their buffers.
     if (root < 0 || root >= g->n) fail(BFS_E_ROOT_RANGE, "root out of range");
     if (w->words * 32 < g->n || w->words % 64 != 0) fail(BFS_E_INTERNAL, "workspace bitmaps too small");
@@ -1653,9 +1666,9 @@ void launch_single(bfs_graph* g, const bfs_tunables& t, Workspace* w, int32_t ro
 #define BFS_LAUNCH(OFFT, BS)                                         \
     do {                                                             \
         if (atomic)                                                  \
-            launch_typed<OFFT, BS, true>(g, t, w, p, s);             \
+            launch_typed<OFFT, BS, true>(g, t, w, p, s, stop);       \
         else                                                         \
-            launch_typed<OFFT, BS, false>(g, t, w, p, s);            \
+            launch_typed<OFFT, BS, false>(g, t, w, p, s, stop);      \
     } while (0)
     if (off32) {
         if (t.block_size == 1024)

@@ -70,8 +70,8 @@ def main() -> int:
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(the batched and serving patterns shard by replicating graphs per GPU; see DESIGN.md)",
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
+              "(batched and served BFS would shard by replicating each graph on every GPU)",
               file=sys.stderr)
         return 2
 

@@ -264,3 +264,20 @@ def test_hot_layout_ragged_vertex_count(hot, flags):
     roots += [int(r) for r in graphgen.pick_roots(g, 2, seed=62)]
     for r in roots:
         check_root(g, dg, r, flags=flags)
+
+
+@pytest.mark.parametrize("flags", [0, bfs.BFS_HYBRID])
+def test_depth_changes_between_runs(flags):
+    """Roots of very different depths, alternately, on one workspace of a graph
+    with the degree-ordered copy: a run deeper than the previous one outlives
+    the first chunk of levels, which already wrote its outputs and stop event,
+    and must write both again at its end. Levels exact, parents valid, and a
+    positive time every run."""
+    g = graphgen.disjoint(graphgen.rmat(14, 16, seed=63), graphgen.path(300))
+    dg = load(g, symmetric=True)
+    bfs.bfs_graph_set_tunables(dg, hot_vertices=512, block_size=1024)
+    shallow = int(graphgen.pick_roots(graphgen.rmat(14, 16, seed=63), 1, seed=64)[0])
+    deep = g.n - 1  # one end of the path: 299 levels below it
+    for r in (shallow, deep, shallow, shallow, deep, deep, shallow):
+        _, _, st = check_root(g, dg, r, flags=flags)
+        assert st["device_ms"] > 0.0

@@ -34,11 +34,17 @@
  *   oracle_certify   The same verdict without running a BFS, for outputs too
  *                    large to recompute one by one: V2-V4 plus V5, every arc
  *                    u -> v leaving a reached u reaches v with
- *                    levels[v] <= levels[u] + 1. The parent chain of V4 bounds
- *                    levels[v] from below by the hop distance (it is a walk of
- *                    levels[v] arcs from the root) and V5 applied along a
- *                    shortest path bounds it from above, so V2-V5 hold exactly
- *                    when levels[] is the hop distance and parents[] a BFS tree.
+ *                    levels[v] <= levels[u] + 1. V4 asks every reached vertex
+ *                    other than the root for a level of at least 1 and a
+ *                    parent one level lower; following parents therefore
+ *                    lowers the level by one per arc until it reaches level 0,
+ *                    which only the root holds (V2 and V4), so every reached v
+ *                    has a walk of levels[v] arcs from the root and
+ *                    levels[v] >= its hop distance. V5 applied along a shortest
+ *                    path from the root shows every vertex on it reached with
+ *                    levels[v] <= its hop distance. Hence V2-V5 hold exactly
+ *                    when levels[] is the hop distance (-1 where unreachable)
+ *                    and parents[] a BFS tree, on directed graphs as well.
  *
  *   oracle_min_parents  Deterministic predecessors. Any reached neighbour one
  *                    layer up is a correct predecessor (section 3.2), so the
@@ -51,7 +57,13 @@
  * Pins: tests/test_oracle_*.py check this file against brute force on every
  * labelled graph with n <= 6, unit-weight Bellman-Ford on random digraphs,
  * closed forms (path, cycle, star, complete graph, grid, binary tree, disjoint
- * components) and the paper's worked examples.
+ * components) and the paper's worked examples. The two checkers are pinned by
+ * tests/test_validator.py: over every digraph on 3 vertices they accept exactly
+ * the candidate outputs (all levels and parents in -1..2) that equal the
+ * matrix-power distances and pass a pure-Python tree check, and on random
+ * directed and symmetric graphs they judge every single planted change of a
+ * level or a parent as that check does. Planted mistakes in copies of this
+ * file (tests/test_oracle_mutants.py) must each fail one of these pins.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -120,7 +132,9 @@ static int has_arc(const int64_t* offsets, const int32_t* cols, int64_t u, int32
     return lo < offsets[u + 1] && cols[lo] == v;
 }
 
-/* V2-V4 of a candidate against its own levels (shared by both checks). */
+/* V2-V4 of a candidate against its own levels (shared by both checks). V4
+ * includes the level bound: a reached vertex other than the root sits at
+ * level 1 or deeper, so its parent is itself reached. */
 static int check_tree(int64_t n, const int64_t* offsets, const int32_t* cols, int64_t root,
                       const int32_t* levels, const int32_t* parents, int rows_sorted,
                       int64_t* bad_vertex) {
@@ -137,7 +151,7 @@ static int check_tree(int64_t n, const int64_t* offsets, const int32_t* cols, in
     for (int64_t v = 0; v < n; ++v) { /* V4 */
         if (v == root || levels[v] == -1) continue;
         int64_t u = parents[v];
-        if (u < 0 || u >= n || levels[u] != levels[v] - 1 ||
+        if (levels[v] < 1 || u < 0 || u >= n || levels[u] != levels[v] - 1 ||
             !has_arc(offsets, cols, u, (int32_t)v, rows_sorted)) {
             if (bad_vertex) *bad_vertex = v;
             return 4;

@@ -349,3 +349,158 @@ def pin_min_parents(lib) -> list[str]:
         if not np.array_equal(pa, ref):
             fails.append(f"digraph n={n} root {r}: least parents differ")
     return fails
+
+
+# ---------------------------------------------------------------------------
+# The checkers themselves (validate: V1-V4 against reference levels; certify:
+# V2-V5 on its own). A candidate is correct exactly when its levels are the hop
+# distances and its parents a BFS tree (the paper's section 3.2: any discoverer
+# one layer up is a correct predecessor); both checkers must accept exactly the
+# correct candidates.
+# ---------------------------------------------------------------------------
+
+def all_digraph_adjacency(n: int) -> np.ndarray:
+    """Adjacency matrices of every labelled digraph on n vertices without self-loops."""
+    off = [(i, j) for i in range(n) for j in range(n) if i != j]
+    k = len(off)
+    masks = np.arange(1 << k, dtype=np.int64)
+    bits = ((masks[:, None] >> np.arange(k)) & 1).astype(bool)
+    adj = np.zeros((1 << k, n, n), dtype=bool)
+    adj[:, [a for a, _ in off], [b for _, b in off]] = bits
+    return adj
+
+
+def _checker_calls(lib, n, offsets, cols, root, ref, rows_sorted):
+    """Two callables (validate, certify) taking candidate arrays written in place
+    into fixed buffers: one ctypes call per candidate, no conversions."""
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    col = np.ascontiguousarray(cols, dtype=np.int32)
+    if col.size == 0:
+        col = np.zeros(1, dtype=np.int32)
+    rl = np.ascontiguousarray(ref, dtype=np.int32)
+    lv = np.zeros(n, dtype=np.int32)
+    pa = np.zeros(n, dtype=np.int32)
+    bad = np.zeros(1, dtype=np.int64)
+    po, pc, pr, pl, pp, pb = (a.ctypes.data for a in (off, col, rl, lv, pa, bad))
+    srt = int(bool(rows_sorted))
+
+    def validate(levels, parents):
+        lv[:] = levels
+        pa[:] = parents
+        return lib.oracle_validate(n, po, pc, root, pr, pl, pp, srt, pb)
+
+    def certify(levels, parents):
+        lv[:] = levels
+        pa[:] = parents
+        return lib.oracle_certify(n, po, pc, root, pl, pp, srt, pb)
+
+    return validate, certify
+
+
+def pin_checkers_exhaustive(lib, n: int = 3) -> list[str]:
+    """Every labelled digraph on n vertices (root 0: relabelling covers the other
+    roots), every candidate with levels and parents in {-1, .., n-1}: validate
+    (given the matrix-power distances) and certify both accept exactly the
+    candidates whose levels equal those distances and whose parents pass the
+    pure-Python tree check."""
+    adj = all_digraph_adjacency(n)
+    dist = matrix_power_levels(adj)
+    vals = np.arange(-1, n)
+    grid = np.array(np.meshgrid(*([vals] * n), indexing="ij")).reshape(n, -1).T  # all value vectors
+    fails = []
+    root = 0
+    for gi in range(adj.shape[0]):
+        src, dst = np.nonzero(adj[gi])
+        offsets = np.zeros(n + 1, dtype=np.int64)
+        np.cumsum(np.bincount(src, minlength=n), out=offsets[1:])
+        cols = dst.astype(np.int32)
+        d = dist[gi, root]
+        validate, certify = _checker_calls(lib, n, offsets, cols, root, d, True)
+        for lvv in grid:
+            same = np.array_equal(lvv, d)
+            for pav in grid:
+                truth = same and check_parents_python(n, offsets, cols, root, lvv, pav)
+                if (validate(lvv, pav) == 0) != truth:
+                    fails.append(f"validate digraph {gi} levels {lvv.tolist()} parents {pav.tolist()}: "
+                                 f"{'rejected' if truth else 'accepted'}")
+                if (certify(lvv, pav) == 0) != truth:
+                    fails.append(f"certify digraph {gi} levels {lvv.tolist()} parents {pav.tolist()}: "
+                                 f"{'rejected' if truth else 'accepted'}")
+                if len(fails) > 5:
+                    return fails
+    return fails
+
+
+def _python_parents(n, offsets, cols, dist, root, pick_max: bool):
+    """A BFS tree from reference distances, chosen without the oracle: the
+    largest (or smallest) in-neighbour one level up."""
+    pa = np.full(n, -1, dtype=np.int64)
+    for u in range(n):
+        if dist[u] < 0:
+            continue
+        for v in cols[offsets[u]:offsets[u + 1]].tolist():
+            if v != root and dist[v] == dist[u] + 1:
+                if pa[v] < 0 or (u > pa[v] if pick_max else u < pa[v]):
+                    pa[v] = u
+    pa[root] = root
+    return pa
+
+
+def pin_checkers_planted(lib, count: int = 40, seed: int = 23) -> list[str]:
+    """Random graphs (directed and symmetric, rows sorted, degrees up to ~12):
+    a correct tree from Bellman-Ford distances is accepted by both checkers, and
+    every single planted change of one level or one parent is judged as the
+    pure-Python check judges it."""
+    rng = np.random.default_rng(seed)
+    fails = []
+    for it in range(count):
+        n = int(rng.integers(4, 24))
+        m = int(rng.integers(n, 6 * n))
+        src = rng.integers(0, n, m).tolist()
+        dst = rng.integers(0, n, m).tolist()
+        sym = bool(it % 2)
+        g = graphgen.from_edges(n, src, dst, symmetric=sym)
+        asrc = np.repeat(np.arange(n), np.diff(g.offsets)).tolist()
+        root = int(rng.integers(0, n))
+        dist = bellman_ford_levels(n, asrc, g.cols.tolist(), root)
+        validate, certify = _checker_calls(lib, n, g.offsets, g.cols, root, dist, True)
+        for pick_max in (False, True):
+            pa = _python_parents(n, g.offsets, g.cols, dist, root, pick_max)
+            if validate(dist, pa) != 0 or certify(dist, pa) != 0:
+                fails.append(f"n={n} root={root}: a correct tree was rejected")
+        base_pa = _python_parents(n, g.offsets, g.cols, dist, root, False)
+        for v in range(n):
+            for val in range(-1, n + 1):
+                for which in ("level", "parent"):
+                    lv = dist.copy()
+                    pa = base_pa.copy()
+                    if which == "level":
+                        if val == lv[v]:
+                            continue
+                        lv[v] = val
+                    else:
+                        if val == pa[v]:
+                            continue
+                        pa[v] = val
+                    truth = np.array_equal(lv, dist) and check_parents_python(n, g.offsets, g.cols, root, lv, pa)
+                    if (validate(lv, pa) == 0) != truth or (certify(lv, pa) == 0) != truth:
+                        fails.append(f"n={n} root={root} {which}[{v}]={val}: misjudged (correct={truth})")
+                    if len(fails) > 5:
+                        return fails
+    return fails
+
+
+def pin_checkers_directed_counterexample(lib) -> list[str]:
+    """Digraph 0->1, 2->3 from root 0: vertex 3 claims level 0 through the
+    unreached vertex 2. Both checkers must reject it."""
+    g = graphgen.from_edges(4, [0, 2], [1, 3], symmetric=False)
+    lv = np.array([0, 1, -1, 0])
+    pa = np.array([0, 0, -1, 2])
+    ref = np.array([0, 1, -1, -1])
+    validate, certify = _checker_calls(lib, 4, g.offsets, g.cols, 0, ref, True)
+    fails = []
+    if certify(lv, pa) == 0:
+        fails.append("certify accepts a second level-0 vertex under an unreached parent")
+    if validate(lv, pa) == 0:
+        fails.append("validate accepts a second level-0 vertex under an unreached parent")
+    return fails

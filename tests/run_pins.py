@@ -14,7 +14,8 @@ def main(path: str) -> int:
     lib = oracle.load_library(path)
     for pin in (lambda: pins.pin_paper_examples(lib), lambda: pins.pin_closed_forms(lib),
                 lambda: pins.pin_exhaustive(lib, 4), lambda: pins.pin_random_digraphs(lib, 20),
-                lambda: pins.pin_min_parents(lib)):
+                lambda: pins.pin_min_parents(lib), lambda: pins.pin_checkers_directed_counterexample(lib),
+                lambda: pins.pin_checkers_exhaustive(lib), lambda: pins.pin_checkers_planted(lib)):
         fails = pin()
         if fails:
             print("PIN FAILED:", fails[0])

@@ -43,6 +43,20 @@ MUTANTS = {
                                    "for (int64_t u = 0; u < n; ++u) {\n        if (levels[u] < 0)"),
     "min_parent_last_arc_dropped": ("for (int64_t j = offsets[u]; j < offsets[u + 1]; ++j) {\n            const int32_t v = cols[j];\n            if (levels[v] != levels[u] + 1)",
                                     "for (int64_t j = offsets[u]; j + 1 < offsets[u + 1]; ++j) {\n            const int32_t v = cols[j];\n            if (levels[v] != levels[u] + 1)"),
+    # The checkers (validate V1-V4, certify V2-V5).
+    "check_level0_bound_dropped": ("if (levels[v] < 1 || u < 0", "if (u < 0"),
+    "check_v3_dropped": ("if ((levels[v] == -1) != (parents[v] == -1)) {", "if (0) {"),
+    "check_v2_root_parent_dropped": ("if (levels[root] != 0 || parents[root] != root) {", "if (levels[root] != 0) {"),
+    "check_parent_level_dropped": ("levels[u] != levels[v] - 1 ||", ""),
+    "check_arc_test_dropped": ("!has_arc(offsets, cols, u, (int32_t)v, rows_sorted)", "0"),
+    "has_arc_search_off_by_one": ("return lo < offsets[u + 1] && cols[lo] == v;",
+                                  "return lo + 1 < offsets[u + 1] && cols[lo] == v;"),
+    "validate_v1_dropped": ("if (levels[v] != ref_levels[v]) {", "if (0) {"),
+    "certify_v5_dropped": ("if (levels[v] == -1 || levels[v] > levels[u] + 1) {", "if (0) {"),
+    "certify_v5_unreached_allowed": ("if (levels[v] == -1 || levels[v] > levels[u] + 1) {",
+                                     "if (levels[v] > levels[u] + 1) {"),
+    "certify_v5_skips_two": ("if (levels[v] == -1 || levels[v] > levels[u] + 1) {",
+                             "if (levels[v] == -1 || levels[v] > levels[u] + 2) {"),
 }
 
 

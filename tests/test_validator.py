@@ -90,3 +90,24 @@ def test_certify_agrees_with_validate_on_small_graphs():
             far = lv == lv.max()
             m[far] = lv.max() + 1     # the deepest layer pushed one level further
             assert oracle.certify(g.offsets, g.cols, r, m, pa)[0] != 0
+
+
+def test_certify_rejects_level0_vertex_under_unreached_parent():
+    """Directed graph 0->1, 2->3 from root 0: a second level-0 vertex whose
+    'parent' is unreached must not pass (its parent chain never reaches the root)."""
+    g = graphgen.from_edges(4, [0, 2], [1, 3], symmetric=False)
+    lv = np.array([0, 1, -1, 0], dtype=np.int32)
+    pa = np.array([0, 0, -1, 2], dtype=np.int32)
+    assert oracle.certify(g.offsets, g.cols, 0, lv, pa) == (4, 3)
+    ref, _, _ = oracle.bfs(g.offsets, g.cols, 0)
+    assert ref.tolist() == [0, 1, -1, -1]
+    assert oracle.validate(g.offsets, g.cols, 0, ref, lv, pa)[0] == 1
+
+
+def test_checkers_accept_exactly_the_correct_candidates():
+    """Exhaustive over every digraph on 3 vertices and every candidate output,
+    plus single planted changes on random graphs (see tests/pins.py)."""
+    lib = oracle._load()
+    assert pins.pin_checkers_exhaustive(lib) == []
+    assert pins.pin_checkers_planted(lib) == []
+    assert pins.pin_checkers_directed_counterexample(lib) == []

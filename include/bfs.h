@@ -150,14 +150,21 @@ int bfs_graph_load_csr(int64_t n, int64_t nnz, const void* offsets, const int32_
                        uint32_t flags, bfs_graph** out);
 
 /* Release a graph and every buffer the library allocated for it.
- * BFS_E_BUSY if a server still holds it. NULL is accepted (no-op). */
+ * BFS_E_BUSY if a server still holds it or a run on it is in progress on
+ * another thread. NULL is accepted (no-op). */
 int bfs_graph_free(bfs_graph* g);
 
 /* Size of a resident graph; any output pointer may be NULL. device_bytes counts
  * library-owned device memory (CSR copy, hub table, cached workspaces). */
 int bfs_graph_info(const bfs_graph* g, int64_t* n, int64_t* nnz, int64_t* device_bytes);
 
-/* Read or replace the tunables used by later runs on this graph. */
+/* Read or replace the tunables used by later runs on this graph. Replacing them
+ * may rebuild tables shared by every run on the graph (the big-row table, the
+ * degree-ordered copy) and drops cached workspaces, so it returns BFS_E_BUSY
+ * while a server holds the graph or a run on it is in progress on another
+ * thread; it waits for asynchronous runs already enqueued (BFS_ASYNC) to finish
+ * before rebuilding. BFS_E_INVALID_ARG for a combination that cannot run
+ * (lds_visited on with a bitmap too large for LDS). */
 int bfs_graph_get_tunables(const bfs_graph* g, bfs_tunables* t);
 int bfs_graph_set_tunables(bfs_graph* g, const bfs_tunables* t);
 
@@ -207,6 +214,8 @@ int bfs_run_batch(bfs_graph* g, const int32_t* roots, int32_t num_roots, int32_t
  * the fastest (also applied to the graph). mode 0 tunes bfs_run, mode 1 tunes
  * bfs_run_batch. Candidate results are checked against the default
  * configuration's levels; a candidate that differs is rejected. best may be NULL.
+ * Changes the graph's tunables as bfs_graph_set_tunables does, with the same
+ * BFS_E_BUSY rule (a graph held by a server cannot be tuned).
  */
 int bfs_autotune(bfs_graph* g, const int32_t* roots, int32_t num_roots, int32_t mode,
                  bfs_tunables* best);
@@ -219,12 +228,11 @@ typedef struct {
     int32_t num_streams;            /* HIP streams shared by instances; 0 = 16 */
     int32_t max_instances_per_graph;/* concurrent instances of one graph; 0 = 3 */
     int32_t flags;                  /* reserved, must be 0 */
-    int32_t single_workers;         /* threads that serve lightly loaded graphs with single-root
-                                       runs (bfs_run), each on its own stream; 0 or -1 = none:
-                                       every request is batched (the default) */
-    int32_t batch_min_queue;        /* while fewer than this many requests of a graph wait, the
-                                       next one goes to an idle single-root worker; a longer
-                                       backlog is batched into instances; 0 = 4 */
+    int32_t single_workers;         /* reserved: must be 0 or -1 (every request is batched). A
+                                       value above 0 asked for threads serving lightly loaded
+                                       graphs with single-root runs; that route is disabled and
+                                       bfs_server_create returns BFS_E_INVALID_ARG for it */
+    int32_t batch_min_queue;        /* reserved for the single-root route (>= 0; ignored) */
 } bfs_server_config;
 
 typedef struct {

@@ -116,7 +116,7 @@ int bfs_graph_info(const bfs_graph* g, int64_t* n, int64_t* nnz, int64_t* device
 int bfs_graph_get_tunables(const bfs_graph* g, bfs_tunables* t) {
     return guarded([&] {
         if (!g || !t) bfs::fail(BFS_E_INVALID_ARG, "NULL argument");
-        *t = bfs::resolve_tunables(g, g->tun);
+        *t = bfs::current_tunables(const_cast<bfs_graph*>(g));
         return BFS_OK;
     });
 }
@@ -143,8 +143,8 @@ int bfs_run(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents, void*
         if (hybrid && !g->symmetric) bfs::fail(BFS_E_INVALID_ARG, "BFS_HYBRID needs a graph loaded with BFS_LOAD_SYMMETRIC");
         DeviceScope ds(g->device);
         hipStream_t s = static_cast<hipStream_t>(stream);
-        const bfs_tunables t = bfs::resolve_tunables(g, g->tun);
-        bfs::Workspace* w = bfs::acquire_ws(g, s);
+        bfs_tunables t{};
+        bfs::Workspace* w = bfs::acquire_ws(g, s, &t);
         try {
             int32_t* lv = levels;
             int32_t* pa = parents;
@@ -206,9 +206,9 @@ int bfs_run_batch(bfs_graph* g, const int32_t* roots, int32_t num_roots, int32_t
             if (roots[i] < 0 || roots[i] >= g->n) bfs::fail(BFS_E_ROOT_RANGE, "root out of range");
         DeviceScope ds(g->device);
         hipStream_t s = static_cast<hipStream_t>(stream);
-        const bfs_tunables t = bfs::resolve_tunables(g, g->tun);
+        bfs_tunables t{};
+        bfs::MsWorkspace* w = bfs::acquire_ms(g, s, &t);
         const int width = std::max(1, std::min(64, (int)t.batch_width));
-        bfs::MsWorkspace* w = bfs::acquire_ms(g, s);
         int64_t reached = 0, arcs = 0;
         int32_t nlev = 0;
         double total_ms = 0;

@@ -34,7 +34,7 @@ void apply(bfs_graph* g, const bfs_tunables& t) { apply_tunables(g, resolve_tuna
 // Time one candidate; fills `levels` (n per root, host) when not null.
 double time_single(bfs_graph* g, const int32_t* roots, int count, hipStream_t s, int32_t* lv, int32_t* pa,
                    std::vector<int32_t>* levels) {
-    const bfs_tunables t = resolve_tunables(g, g->tun);
+    const bfs_tunables t = current_tunables(g);
     hipEvent_t a, b;
     hip_check(hipEventCreate(&a), "hipEventCreate");
     hip_check(hipEventCreate(&b), "hipEventCreate");
@@ -70,7 +70,7 @@ double time_single(bfs_graph* g, const int32_t* roots, int count, hipStream_t s,
 
 double time_batch(bfs_graph* g, const int32_t* roots, int count, hipStream_t s, int32_t* lv, int32_t* pa,
                   std::vector<int32_t>* levels) {
-    const bfs_tunables t = resolve_tunables(g, g->tun);
+    const bfs_tunables t = current_tunables(g);
     const int width = std::max(1, std::min(64, (int)t.batch_width));
     hipEvent_t a, b;
     hip_check(hipEventCreate(&a), "hipEventCreate");

@@ -188,8 +188,9 @@ struct bfs_graph {
     // Degree-ordered copy for single-root runs with an LDS hot bitmap.
     std::unique_ptr<bfs::HotLayout> hot;
 
-    bfs_tunables tun{};
+    bfs_tunables tun{};     // guarded by mu
     std::mutex mu;
+    int ws_out = 0;         // workspaces checked out (single-root and multi-source), guarded by mu
     std::vector<bfs::Workspace*> ws_free;
     std::vector<bfs::Workspace*> ws_all;
     std::vector<bfs::MsWorkspace*> ms_free;
@@ -203,8 +204,11 @@ namespace bfs {
 bfs_tunables default_tunables(const bfs_graph* g);
 bfs_tunables resolve_tunables(const bfs_graph* g, const bfs_tunables& t);
 // Make the graph's derived tables match resolved tunables `r` (big-row tables
-// of both orders, the degree-ordered copy) and store them. Waits for in-flight
-// work first when anything has to be rebuilt. Caller must not hold g->mu.
+// of both orders, the degree-ordered copy) and store them. BFS_E_BUSY while a
+// server holds the graph or any workspace is checked out (a run in progress on
+// another thread, a server instance): rebuilding would free memory those use.
+// Waits for in-flight asynchronous work first when anything has to be rebuilt.
+// Caller must not hold g->mu.
 void apply_tunables(bfs_graph* g, const bfs_tunables& r);
 void build_big_table(bfs::BigTable& t, const void* d_off, bool off32, int64_t n, int32_t threshold, int restore_grid,
                      int cu_count, int64_t* max_degree);
@@ -233,10 +237,16 @@ constexpr int kSmallSeg = 64;      // listed next-frontier ids per restore block
 constexpr int kSmallMax = 4096;    // largest frontier the single-workgroup level kernel takes
 int restore_grid_for(int64_t words, int cu_count);
 
-Workspace* acquire_ws(bfs_graph* g, hipStream_t s);
+// Workspaces are checked out under g->mu; `t` (nullable) receives the graph's
+// resolved tunables read under the same lock, so a run's tunables and the
+// derived tables they select cannot change while it holds the workspace
+// (apply_tunables refuses with BFS_E_BUSY while any workspace is out).
+Workspace* acquire_ws(bfs_graph* g, hipStream_t s, bfs_tunables* t = nullptr);
 void release_ws(bfs_graph* g, Workspace* w, hipStream_t s);
-MsWorkspace* acquire_ms(bfs_graph* g, hipStream_t s);
+MsWorkspace* acquire_ms(bfs_graph* g, hipStream_t s, bfs_tunables* t = nullptr);
 void release_ms(bfs_graph* g, MsWorkspace* w, hipStream_t s);
+// The graph's resolved tunables, read under g->mu.
+bfs_tunables current_tunables(bfs_graph* g);
 void free_workspaces(bfs_graph* g);
 
 // Launchers (the kernels live in single.hip and multi.hip).

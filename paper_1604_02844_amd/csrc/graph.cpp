@@ -253,16 +253,20 @@ int64_t lds_visited_words(const bfs_graph* g, const bfs_tunables& t) {
 void apply_tunables(bfs_graph* g, const bfs_tunables& r) {
     if (r.lds_visited > 0 && hot_count(g, r) == 0 && padded_words(g->n) > lds_visited_words_max(r.block_size))
         fail(BFS_E_INVALID_ARG, "the visited bitmap does not fit in LDS beside this workgroup size");
+    // Held for the whole call: a run that starts meanwhile waits in acquire_ws
+    // and then sees the new tunables and tables together.
+    std::lock_guard<std::mutex> lk(g->mu);
+    if (g->server_refs.load() > 0) fail(BFS_E_BUSY, "graph is registered with a server");
+    if (g->ws_out > 0) fail(BFS_E_BUSY, "a run on this graph is in progress");
     const int32_t want_hot = hot_count(g, r);
     const bool big_stale = r.wave_max_degree != g->big.threshold;
     const bool hot_stale = want_hot != (g->hot ? g->hot->hot : 0) ||
                            (g->hot && g->hot->big.threshold != r.wave_max_degree);
     if (big_stale || hot_stale) {
         // Tables are shared by every run on the graph: rebuild them only after
-        // in-flight work has drained. Workspaces hold lists sized for the old
-        // tables: drop them.
+        // in-flight asynchronous work has drained. Workspaces hold lists sized
+        // for the old tables: drop them (none is checked out).
         BFS_HIP(hipDeviceSynchronize());
-        std::lock_guard<std::mutex> lk(g->mu);
         for (auto* w : g->ws_all) g->device_bytes -= w->bytes;
         for (auto* w : g->ms_all) g->device_bytes -= w->bytes;
         free_workspaces(g);
@@ -284,6 +288,11 @@ void apply_tunables(bfs_graph* g, const bfs_tunables& r) {
         }
     }
     g->tun = r;
+}
+
+bfs_tunables current_tunables(bfs_graph* g) {
+    std::lock_guard<std::mutex> lk(g->mu);
+    return resolve_tunables(g, g->tun);
 }
 
 bfs_tunables default_tunables(const bfs_graph* g) {
@@ -345,17 +354,21 @@ bfs_tunables resolve_tunables(const bfs_graph* g, const bfs_tunables& in) {
 // stream that used it; the next user on another stream waits for that event.
 // ---------------------------------------------------------------------------
 
-Workspace* acquire_ws(bfs_graph* g, hipStream_t s) {
+Workspace* acquire_ws(bfs_graph* g, hipStream_t s, bfs_tunables* t) {
+    std::lock_guard<std::mutex> lk(g->mu);
     Workspace* w = nullptr;
-    {
-        std::lock_guard<std::mutex> lk(g->mu);
-        if (!g->ws_free.empty()) {
-            w = g->ws_free.back();
-            g->ws_free.pop_back();
+    if (!g->ws_free.empty()) {
+        w = g->ws_free.back();
+        g->ws_free.pop_back();
+        if (w->used) {
+            const hipError_t e = hipStreamWaitEvent(s, w->ev_free, 0);
+            if (e != hipSuccess) {
+                g->ws_free.push_back(w);
+                hip_check(e, "hipStreamWaitEvent");
+            }
         }
-    }
-    if (w) {
-        if (w->used) BFS_HIP(hipStreamWaitEvent(s, w->ev_free, 0));
+        if (t) *t = resolve_tunables(g, g->tun);
+        ++g->ws_out;
         return w;
     }
     w = new Workspace();
@@ -402,9 +415,10 @@ Workspace* acquire_ws(bfs_graph* g, hipStream_t s) {
         delete w;
         throw;
     }
-    std::lock_guard<std::mutex> lk(g->mu);
     g->ws_all.push_back(w);
     g->device_bytes += w->bytes;
+    if (t) *t = resolve_tunables(g, g->tun);
+    ++g->ws_out;
     return w;
 }
 
@@ -412,19 +426,24 @@ void release_ws(bfs_graph* g, Workspace* w, hipStream_t s) {
     if (hipEventRecord(w->ev_free, s) == hipSuccess) w->used = true;
     std::lock_guard<std::mutex> lk(g->mu);
     g->ws_free.push_back(w);
+    --g->ws_out;
 }
 
-MsWorkspace* acquire_ms(bfs_graph* g, hipStream_t s) {
+MsWorkspace* acquire_ms(bfs_graph* g, hipStream_t s, bfs_tunables* t) {
+    std::lock_guard<std::mutex> lk(g->mu);
     MsWorkspace* w = nullptr;
-    {
-        std::lock_guard<std::mutex> lk(g->mu);
-        if (!g->ms_free.empty()) {
-            w = g->ms_free.back();
-            g->ms_free.pop_back();
+    if (!g->ms_free.empty()) {
+        w = g->ms_free.back();
+        g->ms_free.pop_back();
+        if (w->used) {
+            const hipError_t e = hipStreamWaitEvent(s, w->ev_free, 0);
+            if (e != hipSuccess) {
+                g->ms_free.push_back(w);
+                hip_check(e, "hipStreamWaitEvent");
+            }
         }
-    }
-    if (w) {
-        if (w->used) BFS_HIP(hipStreamWaitEvent(s, w->ev_free, 0));
+        if (t) *t = resolve_tunables(g, g->tun);
+        ++g->ws_out;
         return w;
     }
     w = new MsWorkspace();
@@ -451,9 +470,10 @@ MsWorkspace* acquire_ms(bfs_graph* g, hipStream_t s) {
         delete w;
         throw;
     }
-    std::lock_guard<std::mutex> lk(g->mu);
     g->ms_all.push_back(w);
     g->device_bytes += w->bytes;
+    if (t) *t = resolve_tunables(g, g->tun);
+    ++g->ws_out;
     return w;
 }
 
@@ -461,6 +481,7 @@ void release_ms(bfs_graph* g, MsWorkspace* w, hipStream_t s) {
     if (hipEventRecord(w->ev_free, s) == hipSuccess) w->used = true;
     std::lock_guard<std::mutex> lk(g->mu);
     g->ms_free.push_back(w);
+    --g->ws_out;
 }
 
 void free_workspaces(bfs_graph* g) {
@@ -559,6 +580,10 @@ bfs_graph* load_csr(int64_t n, int64_t nnz, const void* offsets, const int32_t* 
 
 void free_graph(bfs_graph* g) {
     if (g->server_refs.load() > 0) fail(BFS_E_BUSY, "graph is registered with a server");
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        if (g->ws_out > 0) fail(BFS_E_BUSY, "a run on this graph is in progress");
+    }
     (void)hipDeviceSynchronize();
     free_workspaces(g);
     if (g->owns) {

@@ -685,7 +685,7 @@ void ms_join(bfs_graph* g, MsWorkspace* w, const int32_t* slots, const int32_t* 
         stage[64 + i] = roots[i];
     }
     BFS_HIP(hipMemcpyAsync(d_stage, stage, 128 * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    const bfs_tunables t = resolve_tunables(g, g->tun);
+    const bfs_tunables t = current_tunables(g);
     MsParams p = make_params(g, t, w, lvl);
     if (g->off32)
         k_ms_seed<int32_t><<<1, 64, 0, s>>>(p, d_stage, d_stage + 64, count, lvl);

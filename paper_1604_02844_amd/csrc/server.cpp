@@ -267,7 +267,7 @@ void launch_step(GraphState& gs, Instance* in) {
         in->join_roots.clear();
         in->join_bufs.clear();
     }
-    const bfs_tunables t = bfs::resolve_tunables(gs.g, gs.g->tun);
+    const bfs_tunables t = bfs::current_tunables(gs.g);
     bfs::ms_step_enqueue(gs.g, t, in->w, in->level, in->stream, true);
     bfs::hip_check(hipEventRecord(in->done, in->stream), "hipEventRecord");
     in->in_flight = true;
@@ -402,9 +402,11 @@ int bfs_server_create(const bfs_server_config* cfg, bfs_server** out) {
         if (c.num_streams == 0) c.num_streams = 16;
         if (c.max_instances_per_graph == 0) c.max_instances_per_graph = 3;
         if (c.single_workers < -1 || c.batch_min_queue < 0) return BFS_E_INVALID_ARG;
-        // Single-root workers are opt-in: a serving run that used them ended in
-        // a GPU memory fault whose cause has not been found yet.
-        if (c.single_workers <= 0) c.single_workers = 0;
+        // Single-root workers are refused: a serving run that used them ended in
+        // a GPU memory fault whose cause has not been found, so the route stays
+        // closed until it has been.
+        if (c.single_workers > 0) return BFS_E_INVALID_ARG;
+        c.single_workers = 0;
         if (c.batch_min_queue == 0) c.batch_min_queue = 4;
         auto* s = new bfs_server();
         bfs::hip_check(hipGetDevice(&s->device), "hipGetDevice");
@@ -497,6 +499,9 @@ int bfs_server_poll(bfs_server* s, uint64_t ticket, int32_t* levels, int32_t* pa
         if (r.state == ReqState::Queued || r.state == ReqState::Running) return BFS_PENDING;
         if (r.state == ReqState::Failed) {
             const int status = r.status;
+            // Result rows of a failed request go back to its graph's pool
+            // (their contents are never read; a later request refills them).
+            if (r.buf) s->graphs[(size_t)r.graph_id]->free_bufs.push_back(r.buf);
             s->reqs.erase(it);
             return status;
         }

@@ -86,6 +86,14 @@ def test_null_handles_rejected():
     assert lib.bfs_server_destroy(None) == bfs.BFS_OK
 
 
+def test_server_refuses_single_root_workers():
+    """The single-root worker route is closed (its fault is not explained): the
+    request is refused before any device call."""
+    with pytest.raises(bfs.BfsError) as e:
+        bfs.bfs_server_create(single_workers=2)
+    assert e.value.status == bfs.BFS_E_INVALID_ARG
+
+
 def test_python_binding_raises_with_status():
     with pytest.raises(bfs.BfsError) as e:
         bfs.bfs_graph_load_csr(np.array([0, 1], dtype=np.int64), np.array([3], dtype=np.int32))

@@ -47,8 +47,9 @@ def check(g, root, lv, pa, st=None):
         assert st["latency_ms"] >= st["queue_ms"] >= 0
 
 
-WORKERS_OFF = ("single-root workers are switched off: a serving run with them (8 resident graphs, "
-               "Poisson arrivals) ended in a GPU memory fault whose cause is not found yet")
+WORKERS_OFF = ("single-root workers are refused (bfs_server_create returns BFS_E_INVALID_ARG for "
+               "single_workers > 0): a serving run with them (8 resident graphs, Poisson arrivals) ended "
+               "in a GPU memory fault whose cause is not found yet")
 ROUTES = {
     "batched": {},                                        # every request in a multi-source instance
     "adaptive": pytest.param(dict(single_workers=2), marks=pytest.mark.skip(reason=WORKERS_OFF)),
@@ -206,3 +207,29 @@ def test_server_errors(graphs):
     with pytest.raises(bfs.BfsError) as e:
         bfs.bfs_server_create(max_slots=65)
     assert e.value.status == bfs.BFS_E_INVALID_ARG
+
+
+def test_tunables_locked_while_served(graphs):
+    """A graph held by a server keeps its tunables: replacing them (directly or
+    through the autotuner) would rebuild tables and free workspaces that the
+    server's instances use, so both calls report BFS_E_BUSY until the server is
+    gone; the requests served meanwhile stay correct."""
+    g = graphs[0]
+    dg = load(g)
+    before = bfs.bfs_graph_get_tunables(dg)
+    srv = bfs.bfs_server_create()
+    gid = bfs.bfs_server_add_graph(srv, dg)
+    t = bfs.bfs_server_submit(srv, gid, 1)
+    with pytest.raises(bfs.BfsError) as e:
+        bfs.bfs_graph_set_tunables(dg, wave_max_degree=64)
+    assert e.value.status == bfs.BFS_E_BUSY
+    with pytest.raises(bfs.BfsError) as e:
+        bfs.bfs_autotune(dg, [1, 2], mode=0)
+    assert e.value.status == bfs.BFS_E_BUSY
+    assert bfs.bfs_graph_get_tunables(dg) == before
+    lv, pa, st = wait(srv, t, g.n)
+    check(g, 1, lv, pa, st)
+    bfs.bfs_server_destroy(srv)
+    after = bfs.bfs_graph_set_tunables(dg, wave_max_degree=64)
+    assert after["wave_max_degree"] == 64
+    bfs.bfs_graph_free(dg)

@@ -1,18 +1,21 @@
 #!/usr/bin/env python3
 """Benchmark of the BFS hot path on one MI355X.
 
-Default (--mode single): single-root top-down BFS on an R-MAT graph of scale 20
-(1,048,576 vertices), edgefactor 16, initiator .57/.19/.19/.05, ids permuted,
+Default (--mode single): single-root top-down BFS on an R-MAT graph of scale 24
+(16,777,216 vertices), edgefactor 16, initiator .57/.19/.19/.05, ids permuted,
 symmetrised and deduplicated, int32 columns with int64 offsets, 64 seeded roots
 of degree > 0. One step = one BFS from each of the 64 roots. Printed: one JSON
 line with the harmonic mean of per-root GTEPS (m = arcs/2 of the root's
 component, t = device time of the run from HIP events on the run's stream), the
 roofline object of the BFS (algorithmic bytes per run / average run duration vs
-8 TB/s HBM) and the CPU oracle's rate on a bounded sample of the same roots.
+8 TB/s HBM), the CPU oracle's rate on a bounded sample of the same roots, and a
+`batch` object: 64 roots of an R-MAT scale-22 graph in one multi-source run
+against the same roots one at a time, with its own algorithmic bytes and
+roofline fraction (--no-batch leaves it out).
 
 --mode batch: multi-source BFS (R-MAT scale 22 with 64 roots; Erdos-Renyi 2^22,
 average degree 16, with 8/32/64 roots), aggregate GTEPS against the same roots
-run one at a time.
+run one at a time, each case with its algorithmic bytes and roofline fraction.
 --mode serve: the continuous-batching server on 8 resident graphs, Poisson
 arrivals, Zipf(1.1) graph choice; p50/p99 latency and aggregate GTEPS per rate,
 against the same trace replayed through single-root runs in FIFO order.
@@ -38,12 +41,67 @@ def algorithmic_bytes(n: int, reached: int, arcs: int, levels: int, off_bytes: i
     return 8 * n + 8 * reached + 2 * off_bytes * reached + 4 * arcs + levels * 3 * (n // 8)
 
 
+def batch_algorithmic_bytes(n: int, roots: int, levels: int, rows: int, row_arcs: int, discovered: int,
+                            off_bytes: int) -> int:
+    """Compulsory traffic of one multi-source run of `roots` roots: per level a
+    sweep of the three 64-bit mask arrays (3 * 8n); per active row (a vertex
+    holding any root's frontier bit, counted once per level) two offsets and its
+    4-byte columns; the output rows of every root (8n each); and one level and
+    one parent write per (root, vertex) discovery."""
+    return levels * 24 * n + 2 * off_bytes * rows + 4 * row_arcs + roots * 8 * n + 8 * discovered
+
+
+def batch_active_rows(lv, deg, levels: int):
+    """From a batch's level rows (torch int32 [B, n] on the device; measurement
+    only, after the timed run): per level, the vertices reached by any root at
+    that level and the sum of their degrees. Returns (rows, row_arcs) summed
+    over levels."""
+    rows = arcs = 0
+    for k in range(levels):
+        act = (lv == k).any(0)
+        rows += int(act.sum().item())
+        arcs += int(deg[act].sum().item())
+    return rows, arcs
+
+
+def host_info() -> dict:
+    """CPU model, logical CPUs, CPUs this process may use, RAM and the oracle's
+    compiler, for the CPU baseline record."""
+    import platform
+    import subprocess
+
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    mem_gib = None
+    try:
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal:"):
+                    mem_gib = round(int(line.split()[1]) / 2**20, 1)
+                    break
+    except OSError:
+        pass
+    try:
+        cc = subprocess.run(["gcc", "--version"], capture_output=True, text=True).stdout.splitlines()[0]
+    except (OSError, IndexError):
+        cc = "gcc"
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": len(os.sched_getaffinity(0)),
+            "ram_gib": mem_gib, "compiler": f"{cc}; flags -O2 -fPIC -shared"}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--scale", type=int, default=20)
+    ap.add_argument("--scale", type=int, default=24)
     ap.add_argument("--edgefactor", type=int, default=16)
     ap.add_argument("--roots", type=int, default=64)
     ap.add_argument("--seed", type=int, default=1)
@@ -51,8 +109,11 @@ def parse():
     ap.add_argument("--offsets-i32", action="store_true", help="keep 4-byte offsets on the device")
     ap.add_argument("--hybrid", action="store_true",
                     help="direction-optimising runs (BFS_HYBRID): large levels bottom-up, not top-down")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="single-core seconds of oracle work in the CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="single-core seconds of oracle work in the CPU baseline")
+    ap.add_argument("--cpu-threads", type=int, default=16,
+                    help="most host threads for the CPU baseline (the host CPU share of one GPU)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="leave the R-MAT 22 batched object out of the line")
     ap.add_argument("--tune", action="store_true", help="run the autotuner on 4 roots first")
     ap.add_argument("--tunables", default="", help='JSON object of bfs_tunables fields, e.g. {"update_mode": 2}')
     ap.add_argument("--details", default="", help="write per-root records (JSON) to this path")
@@ -170,24 +231,29 @@ def main() -> int:
     if not args.no_cpu_baseline:
         import oracle
 
-        # The oracle as it stands, one serial queue BFS per host thread, over
-        # passes of the same roots until at least cpu_seconds of single-core
-        # work (capped at 64 passes).
-        threads = min(len(roots), os.cpu_count() or 1, 16)
-        res_all, cwall, used, passes, cpu_s = [], 0.0, 0, 0, 0.0
-        while cpu_s < args.cpu_seconds and passes < 64:
-            res, w, used = oracle.bfs_many(g.offsets, g.cols, roots, threads=threads)
+        # The oracle as it stands: one serial queue BFS per host thread, on
+        # every CPU this process may use up to the host share of one GPU, over
+        # groups of the same roots (in order, wrapping) until at least
+        # cpu_seconds of single-core work.
+        info = host_info()
+        threads = max(1, min(info["usable_cpus"], args.cpu_threads))
+        res_all, cwall, used, cpu_s, at = [], 0.0, 0, 0.0, 0
+        while cpu_s < args.cpu_seconds and len(res_all) < 64 * len(roots):
+            group = [roots[(at + i) % len(roots)] for i in range(threads)]
+            at += threads
+            res, w, used = oracle.bfs_many(g.offsets, g.cols, group, threads=threads)
             res_all += res
             cwall += w
-            passes += 1
             cpu_s += sum(t for _, t, _ in res)
         inv = sum(t / s["edges"] for _, t, s in res_all if s["edges"] > 0)
         cpu = {"value": round(len(res_all) / inv / 1e9, 4) if inv > 0 else 0.0,
                "unit": "GTEPS (harmonic mean over roots)", "cores": used, "kind": "oracle",
-               "sample": f"{passes} passes over the {len(roots)} roots: {len(res_all)} serial queue BFS runs, "
+               "sample": f"{len(res_all)} serial queue BFS runs from the first roots of the same {len(roots)}, "
                          f"{cpu_s:.1f} s of single-core work on {used} threads ({cwall:.2f} s wall); "
-                         f"value = harmonic mean of per-run TEPS on one core",
-               "throughput_gteps": round(sum(s["edges"] for _, _, s in res_all) / cwall / 1e9, 4)}
+                         f"value = harmonic mean of per-run TEPS on one core; threads = the CPUs this process "
+                         f"may use, at most {args.cpu_threads} (the host share of one GPU)",
+               "throughput_gteps": round(sum(s["edges"] for _, _, s in res_all) / cwall / 1e9, 4),
+               "roots_per_s": round(len(res_all) / cwall, 3), "host": info}
 
     out = {
         "metric": "GTEPS (harmonic mean over roots) + % HBM roofline",
@@ -217,6 +283,10 @@ def main() -> int:
                         if args.hybrid else {})},
         "cpu_baseline": cpu,
     }
+    if not args.no_batch:
+        del dg, lv, pa
+        torch.cuda.empty_cache()
+        out["batch"] = batch_case(args, "rmat22", 64, max(args.steps, 1))
     if args.details:
         with open(args.details, "w") as f:
             json.dump({"per_root": per_root, "summary": out}, f, indent=1)
@@ -232,49 +302,82 @@ def _single_times(bfs, dg, roots, lv, pa):
     return out
 
 
-def bench_batch(args) -> int:
+def _batch_graph(name: str, seed: int):
+    import graphgen
+
+    if name == "rmat22":
+        return graphgen.cached("rmat", scale=22, edgefactor=16, seed=seed)
+    if name == "er22_d16":
+        return graphgen.cached("er", n=1 << 22, avg_degree=16, seed=seed)
+    raise ValueError(name)
+
+
+def batch_case(args, name: str, widths, steps: int):
+    """Multi-source runs of the first `b` seeded roots for each width b, against
+    the same roots run one at a time. Per case: the mean device time of `steps`
+    batch runs (after one untimed run), aggregate GTEPS, the algorithmic bytes
+    of one batch run and its roofline fraction. Returns one record, or a list
+    when `widths` is a list."""
     import torch
 
     import graphgen
     import paper_1604_02844_amd as bfs
 
+    one = not isinstance(widths, (list, tuple))
+    widths = [widths] if one else list(widths)
+    g = _batch_graph(name, args.seed)
+    dg = bfs.bfs_graph_load_csr(g.offsets, g.cols)
+    deg = torch.from_numpy(np.diff(g.offsets)).cuda()
+    pool = graphgen.pick_roots(g, max(widths), seed=args.root_seed)
+    lv1 = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    pa1 = torch.empty(g.n, dtype=torch.int32, device="cuda")
+    _single_times(bfs, dg, pool[:2], lv1, pa1)  # warm-up
+    single = _single_times(bfs, dg, pool, lv1, pa1)
+    del lv1, pa1
+    print(f"[bench] {name}: n={g.n} nnz={g.nnz}, single-root runs done", file=sys.stderr, flush=True)
     results = []
-    cases = [("rmat22", lambda: graphgen.cached("rmat", scale=22, edgefactor=16, seed=args.seed), [64]),
-             ("er22_d16", lambda: graphgen.cached("er", n=1 << 22, avg_degree=16, seed=args.seed), [8, 32, 64])]
-    for name, make, widths in cases:
-        g = make()
-        dg = bfs.bfs_graph_load_csr(g.offsets, g.cols)
-        pool = graphgen.pick_roots(g, max(widths), seed=args.root_seed)
-        lv1 = torch.empty(g.n, dtype=torch.int32, device="cuda")
-        pa1 = torch.empty(g.n, dtype=torch.int32, device="cuda")
-        _single_times(bfs, dg, pool[:2], lv1, pa1)  # warm-up
-        single = _single_times(bfs, dg, pool, lv1, pa1)
-        print(f"[bench] {name}: n={g.n} nnz={g.nnz}, single-root runs done", file=sys.stderr, flush=True)
-        for b in widths:
-            lv = torch.empty((b, g.n), dtype=torch.int32, device="cuda")
-            pa = torch.empty((b, g.n), dtype=torch.int32, device="cuda")
-            bfs.bfs_run_batch(dg, pool[:b], lv, pa)  # warm-up
-            best = None
-            for _ in range(max(args.steps, 1)):
-                st = bfs.bfs_run_batch(dg, pool[:b], lv, pa)
-                best = st if best is None or st["device_ms"] < best["device_ms"] else best
-            m_sum = sum(m for _, m in single[:b])
-            t_single = sum(t for t, _ in single[:b])
-            assert best["edges_traversed"] == m_sum, (best, m_sum)
-            rec = {"graph": name, "n": g.n, "nnz": g.nnz, "roots": b, "batch_ms": round(best["device_ms"], 3),
-                   "batch_gteps": round(m_sum / (best["device_ms"] * 1e-3) / 1e9, 2),
-                   "one_at_a_time_ms": round(t_single, 3),
-                   "one_at_a_time_gteps": round(m_sum / (t_single * 1e-3) / 1e9, 2)}
-            rec["speedup"] = round(rec["batch_gteps"] / rec["one_at_a_time_gteps"], 2)
-            results.append(rec)
-            print(f"[bench] {rec}", file=sys.stderr, flush=True)
-            del lv, pa
-        del dg
+    for b in widths:
+        lv = torch.empty((b, g.n), dtype=torch.int32, device="cuda")
+        pa = torch.empty((b, g.n), dtype=torch.int32, device="cuda")
+        bfs.bfs_run_batch(dg, pool[:b], lv, pa)  # warm-up
+        sts = [bfs.bfs_run_batch(dg, pool[:b], lv, pa) for _ in range(steps)]
+        t_ms = sum(st["device_ms"] for st in sts) / len(sts)
+        st = sts[-1]
+        m_sum = sum(m for _, m in single[:b])
+        t_single = sum(t for t, _ in single[:b])
+        assert st["edges_traversed"] == m_sum, (st, m_sum)
+        rows, row_arcs = batch_active_rows(lv, deg, st["num_levels"])
+        b_alg = batch_algorithmic_bytes(g.n, b, st["num_levels"], rows, row_arcs, st["reached"], 8)
+        achieved = b_alg / (t_ms * 1e-3) / 1e9
+        rec = {"graph": name, "n": g.n, "nnz": g.nnz, "roots": b, "batch_ms": round(t_ms, 3),
+               "batch_gteps": round(m_sum / (t_ms * 1e-3) / 1e9, 2),
+               "one_at_a_time_ms": round(t_single, 3),
+               "one_at_a_time_gteps": round(m_sum / (t_single * 1e-3) / 1e9, 2),
+               "levels": st["num_levels"], "active_rows": rows, "active_row_arcs": row_arcs,
+               "bytes_alg": b_alg, "achieved_gbs": round(achieved, 1),
+               "frac": round(achieved / HBM_PEAK_GBS, 4), "runs": len(sts)}
+        rec["speedup"] = round(rec["batch_gteps"] / rec["one_at_a_time_gteps"], 2)
+        results.append(rec)
+        print(f"[bench] {rec}", file=sys.stderr, flush=True)
+        del lv, pa
+    del dg, deg
+    torch.cuda.empty_cache()
+    return results[0] if one else results
+
+
+def bench_batch(args) -> int:
+    results = []
+    for name, widths in (("rmat22", [64]), ("er22_d16", [8, 32, 64])):
+        results += batch_case(args, name, widths, max(args.steps, 1))
     head = next(r for r in results if r["graph"] == "rmat22")
     out = {"metric": "batched multi-source GTEPS (aggregate) vs one root at a time", "value": head["batch_gteps"],
            "unit": "GTEPS", "n_gpus": 1, "steps": args.steps, "higher_is_better": True, "dtype": "int32",
            "data": "synthetic", "config": {"workload": "multi-source BFS, 64-bit bit-sliced masks; R-MAT scale 22 "
                                                        "(64 roots) and Erdos-Renyi 2^22 avg degree 16 (8/32/64 roots)"},
+           "roofline": {"bound": "hbm", "achieved": head["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": head["frac"], "traffic": None,
+                        "kernel": "bfs_run_batch (k_ms_push / k_ms_pull / k_ms_finish per level), R-MAT 22, 64 roots",
+                        "bytes_alg_per_launch": head["bytes_alg"]},
            "cases": results}
     print(json.dumps(out), flush=True)
     return 0

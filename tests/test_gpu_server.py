@@ -233,3 +233,50 @@ def test_tunables_locked_while_served(graphs):
     after = bfs.bfs_graph_set_tunables(dg, wave_max_degree=64)
     assert after["wave_max_degree"] == 64
     bfs.bfs_graph_free(dg)
+
+
+@pytest.mark.slow
+def test_serving_configured_graph_set():
+    """The serving configuration's eight resident graphs (R-MAT scales 16, 18,
+    20, 22, 24 at edgefactor 16; Erdos-Renyi 2^18 d8, 2^20 d16, 2^22 d32), six
+    requests per graph submitted interleaved so that instances of every graph
+    run at once. Every response is checked: against the oracle's levels up to
+    2^22 vertices, by the V2-V5 certificate (exact at any size) above."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    torch_mod()
+    specs = [("rmat", dict(scale=16, edgefactor=16)), ("rmat", dict(scale=18, edgefactor=16)),
+             ("rmat", dict(scale=20, edgefactor=16)), ("rmat", dict(scale=22, edgefactor=16)),
+             ("rmat", dict(scale=24, edgefactor=16)), ("er", dict(n=1 << 18, avg_degree=8)),
+             ("er", dict(n=1 << 20, avg_degree=16)), ("er", dict(n=1 << 22, avg_degree=32))]
+    gs = []
+    for kind, kw in specs:
+        print(f"[case] generating {kind} {kw}", flush=True)
+        gs.append(graphgen.cached(kind, seed=1, **kw))
+    srv = bfs.bfs_server_create()
+    dgs = [load(g) for g in gs]
+    gids = [bfs.bfs_server_add_graph(srv, d) for d in dgs]
+    reqs = []
+    for k in range(6):
+        for i, g in enumerate(gs):
+            root = int(graphgen.pick_roots(g, 6, seed=70 + i)[k])
+            reqs.append((i, root, bfs.bfs_server_submit(srv, gids[i], root)))
+    print(f"[case] serving {len(reqs)} requests over the 8 configured graphs", flush=True)
+
+    def judge(g, root, lv, pa, st):
+        if g.n <= (1 << 22) and g.nnz < 200_000_000:
+            check(g, root, lv, pa, st)
+        else:
+            code, bad = oracle.certify(g.offsets, g.cols, root, lv, pa)
+            assert code == 0, f"{g.name} root {root}: {oracle.CHECK_NAMES[code]} at {bad}"
+            assert st["reached"] == int((lv >= 0).sum())
+
+    futs = []
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        for i, root, t in reqs:
+            lv, pa, st = wait(srv, t, gs[i].n, timeout=300.0)
+            assert st["graph_id"] == gids[i]
+            futs.append(ex.submit(judge, gs[i], root, lv, pa, st))
+        for f in futs:
+            f.result()
+    bfs.bfs_server_destroy(srv)

@@ -221,7 +221,7 @@ def test_tunables_locked_while_served(graphs):
     gid = bfs.bfs_server_add_graph(srv, dg)
     t = bfs.bfs_server_submit(srv, gid, 1)
     with pytest.raises(bfs.BfsError) as e:
-        bfs.bfs_graph_set_tunables(dg, wave_max_degree=64)
+        bfs.bfs_graph_set_tunables(dg, wave_max_degree=1024)
     assert e.value.status == bfs.BFS_E_BUSY
     with pytest.raises(bfs.BfsError) as e:
         bfs.bfs_autotune(dg, [1, 2], mode=0)
@@ -230,8 +230,8 @@ def test_tunables_locked_while_served(graphs):
     lv, pa, st = wait(srv, t, g.n)
     check(g, 1, lv, pa, st)
     bfs.bfs_server_destroy(srv)
-    after = bfs.bfs_graph_set_tunables(dg, wave_max_degree=64)
-    assert after["wave_max_degree"] == 64
+    after = bfs.bfs_graph_set_tunables(dg, wave_max_degree=1024)
+    assert after["wave_max_degree"] == 1024
     bfs.bfs_graph_free(dg)
 
 

@@ -192,6 +192,33 @@ int bfs_graph_set_tunables(bfs_graph* g, const bfs_tunables* t);
 int bfs_run(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents, void* stream,
             uint32_t flags, bfs_run_stats* st);
 
+/*
+ * bfs_run without allocation, for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc). Same kernels and results as bfs_run (levels exact, parents
+ * valid). Every scratch buffer of the run comes from one device array of
+ * BFS_NOALLOC_SCRATCH_BYTES bytes that the library holds on each device it
+ * runs on until the process ends; the caller passes only the graph, the root
+ * and the outputs.
+ *   levels, parents  device int32_t[n] each (host outputs would need staging).
+ *   stream           hipStream_t or NULL; the call returns when the run is done.
+ *   flags            0 or BFS_HYBRID (as for bfs_run).
+ * Calls on one device share the array and are serialised inside the process
+ * (each call completes before the next starts); the array keeps the last
+ * call's contents, and the run clears what must start at zero. Runs on the
+ * graph's current tunables and tables, and, like bfs_run, holds the graph
+ * against bfs_graph_set_tunables for its duration.
+ * Errors: BFS_E_NO_MEMORY when the run needs more scratch than the array
+ * (bitmaps of 3n/8 bytes plus lists, and 8n bytes of run records when the
+ * graph uses the degree-ordered copy): nothing is launched; BFS_E_ROOT_RANGE,
+ * BFS_E_INVALID_ARG (NULL pointers, other flags, BFS_HYBRID on a graph not
+ * loaded as symmetric), BFS_E_DEVICE. No hipMalloc, hipFree, host-pinned
+ * allocation or event creation happens in this call.
+ */
+#define BFS_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+int bfs_run_noalloc(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents, void* stream,
+                    uint32_t flags);
+
 /* ---- batched multi-source BFS --------------------------------------------------- */
 
 /*

@@ -40,10 +40,11 @@ BFS_OUT_HOST = 0x1
 BFS_ASYNC = 0x2
 BFS_HYBRID = 0x4
 BFS_DETERMINISTIC = 0x10
+BFS_NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
 
 ABI_SYMBOLS = [
     "bfs_graph_load_csr", "bfs_graph_free", "bfs_graph_info", "bfs_graph_get_tunables",
-    "bfs_graph_set_tunables", "bfs_run", "bfs_run_batch", "bfs_autotune", "bfs_server_create",
+    "bfs_graph_set_tunables", "bfs_run", "bfs_run_noalloc", "bfs_run_batch", "bfs_autotune", "bfs_server_create",
     "bfs_server_add_graph", "bfs_server_submit", "bfs_server_poll", "bfs_server_destroy",
     "bfs_status_str",
 ]
@@ -123,6 +124,7 @@ def load_library():
         "bfs_graph_get_tunables": [vp, P(Tunables)],
         "bfs_graph_set_tunables": [vp, P(Tunables)],
         "bfs_run": [vp, i32, vp, vp, vp, u32, P(RunStats)],
+        "bfs_run_noalloc": [vp, i32, vp, vp, vp, u32],
         "bfs_run_batch": [vp, vp, i32, vp, vp, vp, u32, P(RunStats)],
         "bfs_autotune": [vp, vp, i32, i32, P(Tunables)],
         "bfs_server_create": [P(ServerConfig), P(vp)],
@@ -280,6 +282,14 @@ def bfs_run(g: Graph, root: int, levels, parents, stream=None, flags: int = 0, s
                                 ctypes.byref(st) if st is not None else None)
     _check(rc, "bfs_run")
     return st.as_dict() if st is not None else None
+
+
+def bfs_run_noalloc(g: Graph, root: int, levels, parents, stream=None, flags: int = 0) -> None:
+    """One BFS with every scratch buffer in the library's static device array.
+    levels/parents: int32 torch CUDA tensors. Returns when the run is done."""
+    rc = load_library().bfs_run_noalloc(g.handle, int(root), _ptr(levels), _ptr(parents), _stream_ptr(stream),
+                                        flags)
+    _check(rc, "bfs_run_noalloc")
 
 
 def bfs_run_batch(g: Graph, roots, levels, parents, stream=None, flags: int = 0, stats: bool = True):

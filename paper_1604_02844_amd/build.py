@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbfs.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
-SOURCES = ["graph.cpp", "abi.cpp", "autotune.cpp", "server.cpp", "single.hip", "multi.hip", "parents.hip"]
+SOURCES = ["graph.cpp", "abi.cpp", "autotune.cpp", "server.cpp", "single.hip", "multi.hip", "parents.hip", "noalloc.hip"]
 ARCH = os.environ.get("BFS_OFFLOAD_ARCH", "gfx950")
 
 # Packed fp32 ops are disabled for all device code (no floating point is used on

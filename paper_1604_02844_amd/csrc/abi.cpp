@@ -10,6 +10,7 @@ namespace bfs {
 bfs_graph* load_csr(int64_t n, int64_t nnz, const void* offsets, const int32_t* cols, uint32_t flags);
 void free_graph(bfs_graph* g);
 void autotune(bfs_graph* g, const int32_t* roots, int32_t num_roots, int32_t mode, bfs_tunables* best);
+void run_noalloc(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents, hipStream_t s, bool hybrid);
 }  // namespace bfs
 
 namespace {
@@ -190,6 +191,19 @@ int bfs_run(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents, void*
             throw;
         }
         bfs::release_ws(g, w, s);
+        return BFS_OK;
+    });
+}
+
+int bfs_run_noalloc(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents, void* stream, uint32_t flags) {
+    return guarded([&] {
+        if (!g || !levels || !parents) bfs::fail(BFS_E_INVALID_ARG, "NULL argument");
+        if (flags & ~BFS_HYBRID) bfs::fail(BFS_E_INVALID_ARG, "bfs_run_noalloc takes BFS_HYBRID only");
+        if (root < 0 || root >= g->n) bfs::fail(BFS_E_ROOT_RANGE, "root out of range");
+        const bool hybrid = flags & BFS_HYBRID;
+        if (hybrid && !g->symmetric) bfs::fail(BFS_E_INVALID_ARG, "BFS_HYBRID needs a graph loaded with BFS_LOAD_SYMMETRIC");
+        DeviceScope ds(g->device);
+        bfs::run_noalloc(g, root, levels, parents, static_cast<hipStream_t>(stream), hybrid);
         return BFS_OK;
     });
 }

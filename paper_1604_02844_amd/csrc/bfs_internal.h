@@ -243,6 +243,10 @@ int restore_grid_for(int64_t words, int cu_count);
 // (apply_tunables refuses with BFS_E_BUSY while any workspace is out).
 Workspace* acquire_ws(bfs_graph* g, hipStream_t s, bfs_tunables* t = nullptr);
 void release_ws(bfs_graph* g, Workspace* w, hipStream_t s);
+// Bytes one single-root workspace of this graph needs (for its current tables).
+// With `base` (256-byte aligned, that many bytes) the workspace's buffers are
+// also carved from it; events and the host mirror are left to the caller.
+size_t ws_layout(const bfs_graph* g, Workspace* w, char* base);
 MsWorkspace* acquire_ms(bfs_graph* g, hipStream_t s, bfs_tunables* t = nullptr);
 void release_ms(bfs_graph* g, MsWorkspace* w, hipStream_t s);
 // The graph's resolved tunables, read under g->mu.

@@ -354,6 +354,40 @@ bfs_tunables resolve_tunables(const bfs_graph* g, const bfs_tunables& in) {
 // stream that used it; the next user on another stream waits for that event.
 // ---------------------------------------------------------------------------
 
+size_t ws_layout(const bfs_graph* g, Workspace* w, char* base) {
+    w->device = g->device;
+    w->words = padded_words(g->n);
+    w->nslots = (int64_t)g->cu_count * 64 + 64;  // >= any expansion or restore grid
+    w->big_capacity = std::max(g->big.num_big, 1);
+    const size_t bmb = (size_t)w->words * 4;
+    const size_t listb = (size_t)w->big_capacity * 8 + (size_t)(g->restore_grid + 1) * 8;
+    w->hot_capacity = (int)std::min<int64_t>(w->words / 16, kMaxHotWords);
+    const size_t hotb = (size_t)w->hot_capacity * 8;  // visited and frontier bits
+    const size_t recb = g->hot ? (size_t)g->n * 8 : 0;  // {level, parent} in the degree-ordered ids
+    const size_t smallb = (size_t)g->restore_grid * (kSmallSeg + 1) * 4;  // listed small frontiers
+    const size_t pre_rec = bmb * 3 + sizeof(Ctrl) + (size_t)w->nslots * 2 * 8 + listb + hotb + smallb;
+    const size_t rec_at = (pre_rec + 255) & ~(size_t)255;
+    const size_t total = rec_at + recb;
+    if (!base) return total;
+    w->vis = reinterpret_cast<uint32_t*>(base);
+    w->vis_prev = w->vis + w->words;
+    w->fr = w->vis_prev + w->words;
+    w->ctrl = reinterpret_cast<Ctrl*>(base + bmb * 3);
+    w->slots = reinterpret_cast<unsigned long long*>(base + bmb * 3 + sizeof(Ctrl));
+    char* lp = base + bmb * 3 + sizeof(Ctrl) + (size_t)w->nslots * 2 * 8;
+    w->bl_u = reinterpret_cast<int32_t*>(lp);
+    w->bl_pre = reinterpret_cast<uint32_t*>(lp + (size_t)w->big_capacity * 4);
+    w->seg_cnt = reinterpret_cast<uint32_t*>(lp + (size_t)w->big_capacity * 8);
+    w->seg_arcs = w->seg_cnt + (g->restore_grid + 1);
+    w->hot_vis = reinterpret_cast<uint32_t*>(lp + listb);
+    w->hot_fr = w->hot_vis + w->hot_capacity;
+    w->run_rec = recb ? reinterpret_cast<int32_t*>(base + rec_at) : nullptr;
+    w->sl = reinterpret_cast<int32_t*>(lp + listb + hotb);
+    w->sl_cnt = w->sl + (size_t)g->restore_grid * kSmallSeg;
+    w->bytes = (int64_t)total;
+    return total;
+}
+
 Workspace* acquire_ws(bfs_graph* g, hipStream_t s, bfs_tunables* t) {
     std::lock_guard<std::mutex> lk(g->mu);
     Workspace* w = nullptr;
@@ -373,42 +407,15 @@ Workspace* acquire_ws(bfs_graph* g, hipStream_t s, bfs_tunables* t) {
     }
     w = new Workspace();
     try {
-        w->device = g->device;
-        w->words = padded_words(g->n);
-        w->nslots = (int64_t)g->cu_count * 64 + 64;  // >= any expansion or restore grid
-        w->big_capacity = std::max(g->big.num_big, 1);
-        const size_t bmb = (size_t)w->words * 4;
-        const size_t listb = (size_t)w->big_capacity * 8 + (size_t)(g->restore_grid + 1) * 8;
-        w->hot_capacity = (int)std::min<int64_t>(w->words / 16, kMaxHotWords);
-        const size_t hotb = (size_t)w->hot_capacity * 8;  // visited and frontier bits
-        const size_t recb = g->hot ? (size_t)g->n * 8 : 0;  // {level, parent} in the degree-ordered ids
-        const size_t smallb = (size_t)g->restore_grid * (kSmallSeg + 1) * 4;  // listed small frontiers
-        const size_t pre_rec = bmb * 3 + sizeof(Ctrl) + (size_t)w->nslots * 2 * 8 + listb + hotb + smallb;
-        const size_t rec_at = (pre_rec + 255) & ~(size_t)255;
-        const size_t total = rec_at + recb;
+        const size_t total = ws_layout(g, w, nullptr);
         char* base = nullptr;
         BFS_HIP(hipMalloc(&base, total));
-        w->vis = reinterpret_cast<uint32_t*>(base);
-        w->vis_prev = w->vis + w->words;
-        w->fr = w->vis_prev + w->words;
-        w->ctrl = reinterpret_cast<Ctrl*>(base + bmb * 3);
-        w->slots = reinterpret_cast<unsigned long long*>(base + bmb * 3 + sizeof(Ctrl));
-        char* lp = base + bmb * 3 + sizeof(Ctrl) + (size_t)w->nslots * 2 * 8;
-        w->bl_u = reinterpret_cast<int32_t*>(lp);
-        w->bl_pre = reinterpret_cast<uint32_t*>(lp + (size_t)w->big_capacity * 4);
-        w->seg_cnt = reinterpret_cast<uint32_t*>(lp + (size_t)w->big_capacity * 8);
-        w->seg_arcs = w->seg_cnt + (g->restore_grid + 1);
-        w->hot_vis = reinterpret_cast<uint32_t*>(lp + listb);
-        w->hot_fr = w->hot_vis + w->hot_capacity;
-        w->run_rec = recb ? reinterpret_cast<int32_t*>(base + rec_at) : nullptr;
-        w->sl = reinterpret_cast<int32_t*>(lp + listb + hotb);
-        w->sl_cnt = w->sl + (size_t)g->restore_grid * kSmallSeg;
+        ws_layout(g, w, base);
         BFS_HIP(hipMemset(w->ctrl, 0, sizeof(Ctrl)));
         BFS_HIP(hipHostMalloc(&w->host_ctrl, sizeof(Ctrl), hipHostMallocDefault));
         BFS_HIP(hipEventCreate(&w->ev_start));
         BFS_HIP(hipEventCreate(&w->ev_stop));
         BFS_HIP(hipEventCreateWithFlags(&w->ev_free, hipEventDisableTiming));
-        w->bytes = (int64_t)total;
     } catch (...) {
         if (w->vis) (void)hipFree(w->vis);
         if (w->host_ctrl) (void)hipHostFree(w->host_ctrl);

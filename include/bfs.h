@@ -128,6 +128,15 @@ typedef struct {
                                    exact atomicOr claims, and consecutive such levels run in one
                                    launch; costs one more launch per level; -1 = off, 0 = library
                                    default (off) */
+    int32_t block_vertices;     /* single-root runs on the degree-ordered copy: rows above T2
+                                   keep their arcs grouped by destination block of this many
+                                   vertices (a power of two from 2^11 to 2^20, rounded down), and
+                                   a level with a large frontier expands those rows block by
+                                   block, each workgroup holding its block's visited bits in LDS
+                                   (exact for earlier levels, so no probe leaves the workgroup
+                                   for them); -1 = off, 0 = library default (off: slower
+                                   at R-MAT scale 24, where a row's arcs split into short
+                                   per-block runs) */
 } bfs_tunables;
 
 /* ---- graph residency ------------------------------------------------------ */

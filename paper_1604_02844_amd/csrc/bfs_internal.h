@@ -164,6 +164,15 @@ struct HotLayout {
     int32_t* d_old2new = nullptr;   // [n] caller id -> run id
     std::vector<int32_t> old2new;   // host copy, for the root
     BigTable big;
+    // Destination blocks of the rows above T2 (all of them hot, so a row's
+    // hot rank indexes its entry): block_vertices as requested (-1 = off);
+    // when nblk > 0 those rows list their columns grouped by block
+    // (id >> blk_shift, ascending) and bseg holds nblk + 1 local arc offsets
+    // per row, the first arc of each block and the degree.
+    int32_t blk_req = -1;
+    int32_t blk_shift = 0;
+    int32_t nblk = 0;
+    uint32_t* d_bseg = nullptr;
     int64_t bytes = 0;
 };
 
@@ -215,11 +224,17 @@ void build_big_table(bfs::BigTable& t, const void* d_off, bool off32, int64_t n,
 void free_big_table(bfs::BigTable& t);
 // Hot vertices used for these tunables (0 = no degree-ordered copy).
 int32_t hot_count(const bfs_graph* g, const bfs_tunables& t);
-void build_hot_layout(bfs_graph* g, int32_t hot, int32_t threshold);
+// `blk`: resolved block_vertices tunable (-1 = no destination blocks).
+void build_hot_layout(bfs_graph* g, int32_t hot, int32_t threshold, int32_t blk);
+// Most destination blocks a grouped row may span (one per lane of a wavefront).
+constexpr int kMaxBlocks = 64;
 void free_hot_layout(bfs_graph* g);
 // Device part of the copy (single.hip): new columns of every new row.
+// Rows above big_threshold are grouped by destination block when nblk > 0
+// (offsets into bseg by hot rank).
 void launch_relabel_cols(const bfs_graph* g, const int64_t* d_noff, const int32_t* d_new2old,
-                         const int32_t* d_old2new, int32_t* d_ncol, int32_t hot_span, int32_t hot_shift);
+                         const int32_t* d_old2new, int32_t* d_ncol, int32_t hot_span, int32_t hot_shift,
+                         int32_t big_threshold, int32_t blk_shift, int32_t nblk, uint32_t* d_bseg);
 int64_t padded_words(int64_t n);
 // Most visited-bitmap words an expansion workgroup of `block` threads can hold
 // in LDS beside its static shared memory.

@@ -154,6 +154,7 @@ void free_hot_layout(bfs_graph* g) {
     if (h.d_col) (void)hipFree(h.d_col);
     if (h.d_new2old) (void)hipFree(h.d_new2old);
     if (h.d_old2new) (void)hipFree(h.d_old2new);
+    if (h.d_bseg) (void)hipFree(h.d_bseg);
     free_big_table(h.big);
     g->device_bytes -= h.bytes;
     g->hot.reset();
@@ -165,7 +166,7 @@ void free_hot_layout(bfs_graph* g) {
 // other vertices fill the remaining ids in increasing caller-id order. Columns are renamed on
 // the device and every row lists its hot neighbours first (each part in the
 // original arc order), so a bottom-up scan meets the likely parents first.
-void build_hot_layout(bfs_graph* g, int32_t hot, int32_t threshold) {
+void build_hot_layout(bfs_graph* g, int32_t hot, int32_t threshold, int32_t blk) {
     free_hot_layout(g);
     if (hot <= 0) return;
     const int64_t n = g->n;
@@ -218,15 +219,33 @@ void build_hot_layout(bfs_graph* g, int32_t hot, int32_t threshold) {
     h->hot = hot;
     h->shift = shift;
     h->span = (int32_t)span;
+    // Destination blocks for the rows above T2: only when every such row is
+    // hot (its hot rank indexes the offsets) and a row spans at most
+    // kMaxBlocks blocks.
+    int64_t num_big = 0;
+    for (int64_t v = 0; v < n; ++v) num_big += (off[(size_t)v + 1] - off[(size_t)v]) > threshold ? 1 : 0;
+    h->blk_req = blk;
+    if (blk > 0 && num_big > 0 && num_big <= hot) {
+        int bs = 0;
+        while (((int64_t)1 << bs) < blk) ++bs;
+        const int64_t nb = (n + ((int64_t)1 << bs) - 1) >> bs;
+        if (nb <= kMaxBlocks) {
+            h->blk_shift = bs;
+            h->nblk = (int32_t)nb;
+        }
+    }
+    const size_t bseg_bytes = h->nblk > 0 ? (size_t)num_big * (size_t)(h->nblk + 1) * 4 : 0;
     try {
         BFS_HIP(hipMalloc(&h->d_off, noff.size() * 8));
         BFS_HIP(hipMalloc(&h->d_col, std::max<size_t>((size_t)g->nnz * 4, 4)));
         BFS_HIP(hipMalloc(&h->d_new2old, (size_t)n * 4));
         BFS_HIP(hipMalloc(&h->d_old2new, (size_t)n * 4));
+        if (bseg_bytes) BFS_HIP(hipMalloc(&h->d_bseg, bseg_bytes));
         BFS_HIP(hipMemcpy(h->d_off, noff.data(), noff.size() * 8, hipMemcpyHostToDevice));
         BFS_HIP(hipMemcpy(h->d_new2old, new2old.data(), (size_t)n * 4, hipMemcpyHostToDevice));
         BFS_HIP(hipMemcpy(h->d_old2new, old2new.data(), (size_t)n * 4, hipMemcpyHostToDevice));
-        launch_relabel_cols(g, h->d_off, h->d_new2old, h->d_old2new, h->d_col, h->span, h->shift);
+        launch_relabel_cols(g, h->d_off, h->d_new2old, h->d_old2new, h->d_col, h->span, h->shift, threshold,
+                            h->blk_shift, h->nblk, h->d_bseg);
         BFS_HIP(hipDeviceSynchronize());
         build_big_table(h->big, h->d_off, false, n, threshold, g->restore_grid, g->cu_count, nullptr);
         if (h->big.num_big != g->big.num_big) fail(BFS_E_INTERNAL, "degree-ordered copy changed the big rows");
@@ -235,11 +254,12 @@ void build_hot_layout(bfs_graph* g, int32_t hot, int32_t threshold) {
         if (h->d_col) (void)hipFree(h->d_col);
         if (h->d_new2old) (void)hipFree(h->d_new2old);
         if (h->d_old2new) (void)hipFree(h->d_old2new);
+        if (h->d_bseg) (void)hipFree(h->d_bseg);
         free_big_table(h->big);
         throw;
     }
     h->old2new = std::move(old2new);
-    h->bytes = (int64_t)noff.size() * 8 + g->nnz * 4 + n * 8 + h->big.bytes;
+    h->bytes = (int64_t)noff.size() * 8 + g->nnz * 4 + n * 8 + h->big.bytes + (int64_t)bseg_bytes;
     g->device_bytes += h->bytes;
     g->hot = std::move(h);
 }
@@ -261,7 +281,8 @@ void apply_tunables(bfs_graph* g, const bfs_tunables& r) {
     const int32_t want_hot = hot_count(g, r);
     const bool big_stale = r.wave_max_degree != g->big.threshold;
     const bool hot_stale = want_hot != (g->hot ? g->hot->hot : 0) ||
-                           (g->hot && g->hot->big.threshold != r.wave_max_degree);
+                           (g->hot && (g->hot->big.threshold != r.wave_max_degree ||
+                                       g->hot->blk_req != r.block_vertices));
     if (big_stale || hot_stale) {
         // Tables are shared by every run on the graph: rebuild them only after
         // in-flight asynchronous work has drained. Workspaces hold lists sized
@@ -276,16 +297,9 @@ void apply_tunables(bfs_graph* g, const bfs_tunables& r) {
                             &g->max_degree);
             g->device_bytes += g->big.bytes;
         }
-        if (want_hot != (g->hot ? g->hot->hot : 0)) {
-            build_hot_layout(g, want_hot, r.wave_max_degree);
-        } else if (g->hot && g->hot->big.threshold != r.wave_max_degree) {
-            HotLayout& h = *g->hot;
-            g->device_bytes -= h.big.bytes;
-            h.bytes -= h.big.bytes;
-            build_big_table(h.big, h.d_off, false, g->n, r.wave_max_degree, g->restore_grid, g->cu_count, nullptr);
-            g->device_bytes += h.big.bytes;
-            h.bytes += h.big.bytes;
-        }
+        // The copy's rows above T2 are grouped by destination block: a new T2
+        // or block size regroups them, so the copy is rebuilt whole.
+        if (hot_stale) build_hot_layout(g, want_hot, r.wave_max_degree, r.block_vertices);
     }
     g->tun = r;
 }
@@ -320,6 +334,9 @@ bfs_tunables default_tunables(const bfs_graph* g) {
                       padded_words(g->n) <= lds_visited_words_max(1024);
     t.lds_visited = fits ? 1 : -1;
     t.sparse_frontier = -1;  // measured slower at R-MAT scale 20 and 24 (see the design notes)
+    // Destination-blocked expansion of the rows above T2: measured slower at
+    // R-MAT scale 24 (the rows' arcs split into short per-block runs), so off.
+    t.block_vertices = -1;
     if (fits) t.block_size = 1024;
     return t;
 }
@@ -346,6 +363,14 @@ bfs_tunables resolve_tunables(const bfs_graph* g, const bfs_tunables& in) {
     if (t.hot_vertices == 0) t.hot_vertices = d.hot_vertices;
     if (t.hot_vertices < 0) t.hot_vertices = -1;
     if (t.hot_vertices > kMaxHotWords * 32) t.hot_vertices = kMaxHotWords * 32;
+    if (t.block_vertices == 0) t.block_vertices = d.block_vertices;
+    if (t.block_vertices < 0) {
+        t.block_vertices = -1;
+    } else {
+        int s = 11;
+        while (s < 20 && ((int64_t)1 << (s + 1)) <= t.block_vertices) ++s;
+        t.block_vertices = 1 << s;
+    }
     return t;
 }
 
@@ -570,7 +595,7 @@ bfs_graph* load_csr(int64_t n, int64_t nnz, const void* offsets, const int32_t* 
                         g->cu_count, &g->max_degree);
         g->device_bytes += g->big.bytes;
         const bfs_tunables t = default_tunables(g);  // depends on the degrees just read
-        build_hot_layout(g, hot_count(g, t), t.wave_max_degree);
+        build_hot_layout(g, hot_count(g, t), t.wave_max_degree, t.block_vertices);
         g->tun = t;
     } catch (...) {
         if (g->owns) {

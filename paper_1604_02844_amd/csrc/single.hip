@@ -91,6 +91,15 @@ struct SingleParams {
     int32_t restore_grid;
     int32_t t1;
     int32_t min_share;         // fewest big-row arcs handed to one workgroup
+    // Rows above T2 grouped by destination block (degree-ordered copy): nblk
+    // blocks of 2^blk_shift vertices; bseg holds nblk + 1 local arc offsets per
+    // row, by hot rank (nullptr: not grouped). Levels whose big rows have at
+    // least blk_min_arcs arcs and whose frontier is large expand them by block.
+    const uint32_t* bseg;
+    int32_t bseg_rows;         // rows in bseg
+    int32_t nblk;
+    int32_t blk_shift;
+    int64_t blk_min_arcs;
     // The 32 * hot_words hot vertices sit at bit positions k << hot_shift of
     // the first hot_span visited words (one per word with shift 5, bits 0 and
     // 16 with shift 4). hot_vis is their compact visited bitmap (slot
@@ -436,21 +445,13 @@ struct ExpandShared {
     uint32_t row0;
 };
 
-// Rows above T2: this workgroup's share [a0, a1) of the level's concatenated
-// big-row arcs. Row metadata is staged BLOCK rows at a time (every thread loads
-// one row); each wavefront then takes a contiguous run of those arcs, 64 x
-// kBigUnroll consecutive arcs per step, so column reads are coalesced. The
-// row boundaries inside a step come from one LDS read per lane (the next 64
-// staged starts) and a ballot; rows above T2 are long, so a step crosses at
-// most a few, and no lane runs a search or a loop of its own.
-template <typename OffT, bool kAtomic, int BLOCK>
-__device__ __forceinline__ void expand_big(const SingleParams& p, ExpandShared<BLOCK>& sh, int64_t a0, int64_t a1,
-                                           int lvl, unsigned long long& arcs, const LdsVis& lds) {
-    constexpr int NW = BLOCK / 64;
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+// Prefix sums over the level's big-row list (one segment per restore block):
+// arcs (segpre) and rows (cntpre), in LDS. Returns the number of listed rows.
+template <int BLOCK>
+__device__ __forceinline__ uint32_t big_prefix(const SingleParams& p, ExpandShared<BLOCK>& sh) {
+    const int tid = threadIdx.x;
     const int R = p.restore_grid;
     constexpr int PER_T = (kMaxRestoreGrid + BLOCK) / BLOCK;  // covers entries 0..R inclusive
-    // Prefix sums over the segments (one per restore block): arcs and rows.
     uint32_t va[PER_T], vc[PER_T];
     uint32_t ma = 0, mc = 0;
 #pragma unroll
@@ -475,52 +476,232 @@ __device__ __forceinline__ void expand_big(const SingleParams& p, ExpandShared<B
         ec += vc[k];
     }
     __syncthreads();
-    const uint32_t total_rows = sh.x.big.cntpre[R];
-    // The row holding arc a0: its segment by the arc prefix, then its index
-    // inside the segment by the stored arc offsets.
-    if (tid == 0) {
-        // Last segment starting at or before a0; as a0 < total, the next
-        // segment starts after a0, so this one holds arcs.
-        int lo = 0, hi = R - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if ((int64_t)sh.x.big.segpre[mid] <= a0)
-                lo = mid;
-            else
-                hi = mid - 1;
-        }
-        const int64_t local = a0 - (int64_t)sh.x.big.segpre[lo];
-        const int first = p.seg_start[lo];
-        int l2 = 0, h2 = (int)(sh.x.big.cntpre[lo + 1] - sh.x.big.cntpre[lo]) - 1;
-        while (l2 < h2) {
-            const int mid = (l2 + h2 + 1) >> 1;
-            if ((int64_t)ld(p.bl_pre + first + mid) <= local)
-                l2 = mid;
-            else
-                h2 = mid - 1;
-        }
-        sh.row0 = sh.x.big.cntpre[lo] + (uint32_t)l2;
+    return sh.x.big.cntpre[R];
+}
+
+// Dense index of the listed row holding arc a (level-wide numbering, a below
+// the level's total): its segment by the arc prefix, then its index inside the
+// segment by the stored arc offsets. One thread.
+template <int BLOCK>
+__device__ __forceinline__ uint32_t big_row_at(const SingleParams& p, const ExpandShared<BLOCK>& sh, int64_t a) {
+    // Last segment starting at or before a; as a < total, the next segment
+    // starts after a, so this one holds arcs.
+    int lo = 0, hi = p.restore_grid - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((int64_t)sh.x.big.segpre[mid] <= a)
+            lo = mid;
+        else
+            hi = mid - 1;
     }
+    const int64_t local = a - (int64_t)sh.x.big.segpre[lo];
+    const int first = p.seg_start[lo];
+    int l2 = 0, h2 = (int)(sh.x.big.cntpre[lo + 1] - sh.x.big.cntpre[lo]) - 1;
+    while (l2 < h2) {
+        const int mid = (l2 + h2 + 1) >> 1;
+        if ((int64_t)ld(p.bl_pre + first + mid) <= local)
+            l2 = mid;
+        else
+            h2 = mid - 1;
+    }
+    return sh.x.big.cntpre[lo] + (uint32_t)l2;
+}
+
+// Listed row d (dense numbering across segments): its vertex and its first arc
+// in the level-wide numbering.
+template <int BLOCK>
+__device__ __forceinline__ void big_row(const SingleParams& p, const ExpandShared<BLOCK>& sh, uint32_t d, int32_t& u,
+                                        int64_t& start) {
+    int lo = 0, hi = p.restore_grid - 1;  // last segment whose first row is <= d (non-empty by construction)
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sh.x.big.cntpre[mid] <= d)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const int slot = p.seg_start[lo] + (int)(d - sh.x.big.cntpre[lo]);
+    u = ld(p.bl_u + slot);
+    start = (int64_t)sh.x.big.segpre[lo] + ld(p.bl_pre + slot);
+}
+
+// The general claim on already-gathered heads v (lanes with ok set): global
+// filter, confirmation on the level array, claim.
+template <bool kAtomic, int U>
+__device__ __forceinline__ void visit_out(const SingleParams& p, const int32_t (&v)[U], const bool (&ok)[U],
+                                          const int32_t (&par)[U], int lvl) {
+#pragma unroll
+    for (int i = 0; i < U; ++i) {
+        const uint32_t b = 1u << (v[i] & 31);
+        if (!ok[i]) continue;
+        if (kAtomic) {
+            if (!(atomicOr(p.vis + (v[i] >> 5), b) & b)) record(p, v[i], lvl, par[i]);
+        } else {
+            const uint32_t w = p.vis[v[i] >> 5];
+            if (!(w & b) && ld(p.lv + lv_at(p, v[i])) == -1) {
+                p.vis[v[i] >> 5] = w | b;  // may lose a concurrent update: restored later
+                record(p, v[i], lvl, par[i]);
+            }
+        }
+    }
+}
+
+// Visit of arcs whose heads all lie in the destination block held in LDS
+// (words [w0, w0 + nw) of the visited bitmap, exact at the start of the
+// level): a set bit is final; a clear one is claimed in LDS first (one claim
+// per workgroup and vertex), then on the global visited word. With
+// update_mode 1 that global claim is an atomicOr at workgroup scope: it
+// executes in the L2 of this XCD, where every workgroup of this block runs
+// (workgroups go to the eight XCDs in turn and pairs are numbered to match),
+// so it is exact among them, cheap, and a lost race with another XCD (there
+// is none for in-block arcs when the assignment holds) only makes a
+// duplicate claim of the same level, which the restoration pass tolerates.
+// With update_mode 2 it is a device-scope atomicOr. A claim needs no
+// confirmation on the level array: the LDS bits already exclude every vertex
+// of an earlier level. An arc outside the block (none, when the grouping
+// holds) takes the confirmed path of visit_arcs.
+template <bool kAtomic, int U>
+__device__ __forceinline__ void visit_blocked(const SingleParams& p, const int64_t (&pos)[U], const bool (&ok)[U],
+                                              const int32_t (&par)[U], int lvl, uint32_t* bits, uint32_t w0,
+                                              uint32_t nw) {
+    int32_t v[U];
+#pragma unroll
+    for (int i = 0; i < U; ++i) v[i] = __builtin_nontemporal_load(p.col + pos[i]);
+    uint32_t lw[U];
+    bool in[U];
+#pragma unroll
+    for (int i = 0; i < U; ++i) {
+        const uint32_t wi = ((uint32_t)v[i] >> 5) - w0;
+        in[i] = wi < nw;
+        lw[i] = bits[in[i] ? wi : 0u];
+    }
+    bool cand[U], any_out = false;
+#pragma unroll
+    for (int i = 0; i < U; ++i) {
+        const uint32_t b = 1u << (v[i] & 31);
+        cand[i] = ok[i] & !(in[i] & ((lw[i] & b) != 0u));
+        if (cand[i] & in[i]) cand[i] = (atomicOr(bits + (((uint32_t)v[i] >> 5) - w0), b) & b) == 0u;
+        any_out |= cand[i] & !in[i];
+    }
+#pragma unroll
+    for (int i = 0; i < U; ++i) {
+        const uint32_t b = 1u << (v[i] & 31);
+        if (cand[i] & in[i]) {
+            const uint32_t old = kAtomic ? atomicOr(p.vis + (v[i] >> 5), b)
+                                         : __hip_atomic_fetch_or(p.vis + (v[i] >> 5), b, __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (!(old & b)) record(p, v[i], lvl, par[i]);
+        }
+    }
+    if (__ballot(any_out)) {
+        // Heads outside the block: the general visit (global filter, level
+        // confirmation, claim), for the lanes that hold such an arc.
+        bool out[U];
+#pragma unroll
+        for (int i = 0; i < U; ++i) out[i] = cand[i] & !in[i];
+        visit_out<kAtomic, U>(p, v, out, par, lvl);
+    }
+}
+
+// Wavefront walk over staged rows: arcs [from, hi_arc) of a numbering in which
+// staged row r starts at sh.x.big.start[r] (non-decreasing; empty rows share
+// their successor's start) and its arc a sits at column index base[r] + a.
+// Each wavefront takes a contiguous run, 64 x kBigUnroll consecutive arcs per
+// step, so column reads are coalesced. The row boundaries inside a step come
+// from one LDS read per lane (the next 64 staged starts) and a ballot; rows
+// are long, so a step crosses at most a few, and no lane runs a search or a
+// loop of its own.
+template <bool kAtomic, int BLOCK, bool kBlocked>
+__device__ __forceinline__ void walk_staged(const SingleParams& p, ExpandShared<BLOCK>& sh, int64_t from,
+                                            int64_t hi_arc, int nt, int lvl, const LdsVis& lds, uint32_t* bits,
+                                            uint32_t w0, uint32_t nw) {
+    constexpr int NW = BLOCK / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int64_t per_w = ((hi_arc - from + NW - 1) / NW + 63) & ~(int64_t)63;
+    const int64_t w_lo = from + (int64_t)wid * per_w;
+    const int64_t w_hi = w_lo + per_w < hi_arc ? w_lo + per_w : hi_arc;
+    if (w_lo >= w_hi) return;
+    int lo = 0, hi = nt - 1;  // last staged row starting at or before w_lo
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sh.x.big.start[mid] <= w_lo) lo = mid; else hi = mid - 1;
+    }
+    int row = lo;  // the same in every lane
+    constexpr int SPAN = 64 * kBigUnroll;
+    for (int64_t ws = w_lo; ws < w_hi; ws += SPAN) {
+        // The next 64 staged row starts, one per lane: those inside this span
+        // are the row boundaries the span crosses (sorted).
+        const int nr = row + 1 + lane;
+        const int64_t x = nr < nt ? sh.x.big.start[nr] : INT64_MAX;
+        const uint64_t inside = __ballot(x < ws + SPAN);
+        const int k = __popcll(inside);  // boundaries before the span's end, all in lanes 0..k-1
+        int64_t pos[kBigUnroll];
+        bool ok[kBigUnroll];
+        int32_t par[kBigUnroll];
+        int r[kBigUnroll];
+#pragma unroll
+        for (int i = 0; i < kBigUnroll; ++i) r[i] = row;
+        int next_row;
+        if (k < 64) {
+            for (int j = 0; j < k; ++j) {  // the same trip count in every lane
+                const int64_t bj = shfl64(x, j);
+#pragma unroll
+                for (int i = 0; i < kBigUnroll; ++i) {
+                    const int64_t a = ws + i * 64 + lane;
+                    r[i] += (a < w_hi ? a : w_hi - 1) >= bj ? 1 : 0;
+                }
+            }
+            next_row = row + __popcll(__ballot(x <= ws + SPAN));
+        } else {
+            // More than 64 rows in one span: each lane moves its own cursor.
+#pragma unroll
+            for (int i = 0; i < kBigUnroll; ++i) {
+                const int64_t a = ws + i * 64 + lane;
+                const int64_t ac = a < w_hi ? a : w_hi - 1;
+                int rr = i == 0 ? row : r[i - 1];
+                while (rr + 1 < nt && sh.x.big.start[rr + 1] <= ac) ++rr;
+                r[i] = rr;
+            }
+            next_row = __shfl(r[kBigUnroll - 1], 63, 64);
+            while (next_row + 1 < nt && sh.x.big.start[next_row + 1] <= ws + SPAN) ++next_row;
+        }
+#pragma unroll
+        for (int i = 0; i < kBigUnroll; ++i) {
+            const int64_t a = ws + i * 64 + lane;
+            ok[i] = a < w_hi;
+            const int64_t ac = ok[i] ? a : w_hi - 1;
+            pos[i] = sh.x.big.base[r[i]] + ac;
+            par[i] = sh.x.big.u[r[i]];
+        }
+        row = next_row;  // the row of the next span's first arc
+        if (kBlocked)
+            visit_blocked<kAtomic, kBigUnroll>(p, pos, ok, par, lvl, bits, w0, nw);
+        else
+            visit_arcs<kAtomic, kBigUnroll>(p, pos, ok, par, lvl, lds);
+    }
+}
+
+// Rows above T2: this workgroup's share [a0, a1) of the level's concatenated
+// big-row arcs. Row metadata is staged BLOCK rows at a time (every thread
+// loads one row); the wavefronts then walk the staged arcs.
+template <typename OffT, bool kAtomic, int BLOCK>
+__device__ __forceinline__ void expand_big(const SingleParams& p, ExpandShared<BLOCK>& sh, int64_t a0, int64_t a1,
+                                           int lvl, unsigned long long& arcs, const LdsVis& lds) {
+    const int tid = threadIdx.x;
+    const uint32_t total_rows = big_prefix<BLOCK>(p, sh);
+    if (tid == 0) sh.row0 = big_row_at<BLOCK>(p, sh, a0);
     __syncthreads();
     uint32_t d0 = sh.row0;
     int64_t from = a0;
     while (from < a1 && d0 < total_rows) {
-        // Stage rows d0 .. d0+BLOCK-1 (dense numbering across segments).
+        // Stage rows d0 .. d0+BLOCK-1.
         const uint32_t d = d0 + (uint32_t)tid;
         const int nt = (int)min((uint32_t)BLOCK, total_rows - d0);
         int64_t end = a1;
         if (tid < nt) {
-            int lo = 0, hi = R - 1;  // last segment whose first row is <= d (non-empty by construction)
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (sh.x.big.cntpre[mid] <= d)
-                    lo = mid;
-                else
-                    hi = mid - 1;
-            }
-            const int slot = p.seg_start[lo] + (int)(d - sh.x.big.cntpre[lo]);
-            const int32_t u = ld(p.bl_u + slot);
-            const int64_t start = (int64_t)sh.x.big.segpre[lo] + ld(p.bl_pre + slot);
+            int32_t u;
+            int64_t start;
+            big_row<BLOCK>(p, sh, d, u, start);
             const int64_t beg = load_off<OffT>(p.off, u);
             const int64_t deg = load_off<OffT>(p.off, (int64_t)u + 1) - beg;
             sh.x.big.start[tid] = start > from ? start : from;
@@ -531,74 +712,101 @@ __device__ __forceinline__ void expand_big(const SingleParams& p, ExpandShared<B
         if (tid == nt - 1) sh.staged_end = end;
         __syncthreads();
         const int64_t hi_arc = sh.staged_end;
-        // Each wavefront takes a contiguous run of the staged arcs and walks
-        // the staged rows with a cursor: a lane's row only moves forward.
-        const int64_t per_w = ((hi_arc - from + NW - 1) / NW + 63) & ~(int64_t)63;
-        const int64_t w_lo = from + (int64_t)wid * per_w;
-        const int64_t w_hi = w_lo + per_w < hi_arc ? w_lo + per_w : hi_arc;
-        if (w_lo < w_hi) {
-            int lo = 0, hi = nt - 1;  // last staged row starting at or before w_lo
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (sh.x.big.start[mid] <= w_lo) lo = mid; else hi = mid - 1;
-            }
-            int row = lo;  // the same in every lane
-            constexpr int SPAN = 64 * kBigUnroll;
-            for (int64_t ws = w_lo; ws < w_hi; ws += SPAN) {
-                // The next 64 staged row starts, one per lane: those inside this
-                // span are the row boundaries the span crosses (sorted, and few:
-                // rows above T2 are long).
-                const int nr = row + 1 + lane;
-                const int64_t x = nr < nt ? sh.x.big.start[nr] : INT64_MAX;
-                const uint64_t inside = __ballot(x < ws + SPAN);
-                const int k = __popcll(inside);  // boundaries before the span's end, all in lanes 0..k-1
-                int64_t pos[kBigUnroll];
-                bool ok[kBigUnroll];
-                int32_t par[kBigUnroll];
-                int r[kBigUnroll];
-#pragma unroll
-                for (int i = 0; i < kBigUnroll; ++i) r[i] = row;
-                int next_row;
-                if (k < 64) {
-                    for (int j = 0; j < k; ++j) {  // the same trip count in every lane
-                        const int64_t bj = shfl64(x, j);
-#pragma unroll
-                        for (int i = 0; i < kBigUnroll; ++i) {
-                            const int64_t a = ws + i * 64 + lane;
-                            r[i] += (a < w_hi ? a : w_hi - 1) >= bj ? 1 : 0;
-                        }
-                    }
-                    next_row = row + __popcll(__ballot(x <= ws + SPAN));
-                } else {
-                    // More than 64 rows in one span (only with a very small T2):
-                    // each lane moves its own cursor forward.
-#pragma unroll
-                    for (int i = 0; i < kBigUnroll; ++i) {
-                        const int64_t a = ws + i * 64 + lane;
-                        const int64_t ac = a < w_hi ? a : w_hi - 1;
-                        int rr = i == 0 ? row : r[i - 1];
-                        while (rr + 1 < nt && sh.x.big.start[rr + 1] <= ac) ++rr;
-                        r[i] = rr;
-                    }
-                    next_row = __shfl(r[kBigUnroll - 1], 63, 64);
-                    while (next_row + 1 < nt && sh.x.big.start[next_row + 1] <= ws + SPAN) ++next_row;
-                }
-#pragma unroll
-                for (int i = 0; i < kBigUnroll; ++i) {
-                    const int64_t a = ws + i * 64 + lane;
-                    ok[i] = a < w_hi;
-                    const int64_t ac = ok[i] ? a : w_hi - 1;
-                    pos[i] = sh.x.big.base[r[i]] + ac;
-                    par[i] = sh.x.big.u[r[i]];
-                }
-                row = next_row;  // the row of the next span's first arc
-                visit_arcs<kAtomic, kBigUnroll>(p, pos, ok, par, lvl, lds);
-            }
-        }
+        walk_staged<kAtomic, BLOCK, false>(p, sh, from, hi_arc, nt, lvl, lds, nullptr, 0u, 0u);
         if (tid == 0) arcs += (unsigned long long)(hi_arc - from);
         from = hi_arc;
         d0 += (uint32_t)nt;
         __syncthreads();
+    }
+}
+
+// Rows above T2 on the degree-ordered copy, whose arcs are grouped by
+// destination block: the level's big-row arcs are cut into C chunks, and the
+// pair (block b, chunk c) goes to one workgroup, which loads block b's visited
+// bits (exact at level start) into LDS and walks, in every staged row of chunk
+// c, only the arcs that fall in block b (a contiguous run of the row, from the
+// row's block offsets). Every probe of such an arc is answered in LDS. Pairs
+// are numbered so that the workgroups of one block run on one XCD (workgroups
+// go to the eight XCDs in turn), where they share the L2 lines of the
+// block's global visited words.
+template <typename OffT, bool kAtomic, int BLOCK>
+__device__ __forceinline__ void expand_blocked(const SingleParams& p, ExpandShared<BLOCK>& sh, int64_t ta, int lvl,
+                                               unsigned long long& arcs, uint32_t* bits) {
+    const int tid = threadIdx.x;
+    const int64_t G = gridDim.x;
+    const int B = p.nblk;
+    const int64_t C = G >= B ? G / B : 1;
+    const int64_t SW = (int64_t)1 << (p.blk_shift - 5);  // visited words per block (a multiple of 64)
+    const uint32_t total_rows = big_prefix<BLOCK>(p, sh);
+    for (int64_t pair = blockIdx.x; pair < (int64_t)B * C; pair += G) {
+        const int b = (int)(pair % B);
+        const int64_t c = pair / B;
+        const int64_t a0 = ta * c / C, a1 = ta * (c + 1) / C;
+        if (a0 >= a1) continue;
+        const int64_t w0 = (int64_t)b * SW;
+        const int64_t nw = SW < p.words - w0 ? SW : p.words - w0;  // multiple of 64
+        __syncthreads();  // the previous pair's probes are done with the LDS bits
+        {
+            const unsigned long long* src = reinterpret_cast<const unsigned long long*>(p.vis_prev + w0);
+            unsigned long long* dst = reinterpret_cast<unsigned long long*>(bits);
+            for (int64_t i = tid; i < nw / 2; i += BLOCK) dst[i] = ld(src + i);
+        }
+        if (tid == 0) sh.row0 = big_row_at<BLOCK>(p, sh, a0);
+        __syncthreads();
+        uint32_t d0 = sh.row0;
+        int64_t from = a0;
+        while (from < a1 && d0 < total_rows) {
+            // Stage rows d0 .. d0+BLOCK-1: the part of each row inside the
+            // chunk and block b, renumbered consecutively.
+            const uint32_t d = d0 + (uint32_t)tid;
+            const int nt = (int)min((uint32_t)BLOCK, total_rows - d0);
+            int64_t end = a1;
+            uint32_t len = 0;
+            int64_t col0 = 0;
+            int32_t uo = 0;
+            if (tid < nt) {
+                int32_t u;
+                int64_t start;
+                big_row<BLOCK>(p, sh, d, u, start);
+                const int64_t beg = load_off<OffT>(p.off, u);
+                const int64_t deg = load_off<OffT>(p.off, (int64_t)u + 1) - beg;
+                const int64_t lo = (from > start ? from : start) - start;
+                const int64_t hi = (a1 < start + deg ? a1 : start + deg) - start;
+                uint32_t rk = 0;
+                const bool listed = hot_slot((uint32_t)u, (uint32_t)p.hot_span, (uint32_t)p.hot_shift, rk) &&
+                                    rk < (uint32_t)p.bseg_rows;
+                // A row without block offsets (none, when the tables agree)
+                // is walked whole by the pairs of block 0, on the confirmed path.
+                int64_t sb = 0, se = b == 0 ? deg : 0;
+                if (listed) {
+                    const uint32_t* sg = p.bseg + (size_t)rk * (size_t)(B + 1);
+                    sb = sg[b];
+                    se = sg[b + 1];
+                }
+                const int64_t elo = lo > sb ? lo : sb, ehi = hi < se ? hi : se;
+                if (ehi > elo) {
+                    len = (uint32_t)(ehi - elo);
+                    col0 = beg + elo;
+                }
+                uo = out_id(p, u);
+                end = start + deg < a1 ? start + deg : a1;
+            }
+            if (tid == nt - 1) sh.staged_end = end;
+            uint32_t excl;
+            const uint32_t tot = block_excl_scan<BLOCK>(len, excl, sh.tmp);
+            if (tid < nt) {
+                sh.x.big.start[tid] = excl;
+                sh.x.big.base[tid] = col0 - (int64_t)excl;
+                sh.x.big.u[tid] = uo;
+            }
+            __syncthreads();
+            walk_staged<kAtomic, BLOCK, true>(p, sh, 0, tot, nt, lvl, LdsVis::none(bits), bits, (uint32_t)w0,
+                                              (uint32_t)nw);
+            if (tid == 0) arcs += (unsigned long long)tot;
+            from = sh.staged_end;
+            d0 += (uint32_t)nt;
+            __syncthreads();
+        }
     }
 }
 
@@ -938,17 +1146,28 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl_arg) {
         }
     }
 
+    extern __shared__ uint32_t hot_lds[];
+    const bool large = (int64_t)sh.found >= p.hot_min_frontier;
+
+    // ---- rows of degree > T2 grouped by destination block (degree-ordered
+    // copy, large levels): block by block, the block's visited bits in LDS
+    bool big_done = false;
+    if (ta > 0 && p.bseg && large && ta >= p.blk_min_arcs) {
+        expand_blocked<OffT, kAtomic, BLOCK>(p, sh, ta, lvl + 1, arcs, hot_lds);
+        big_done = true;
+        __syncthreads();  // the LDS bits are reloaded below
+    }
+
     // ---- LDS copy of visited bits (exact at level start): the compact hot
     // bitmap on the degree-ordered copy, else the whole visited snapshot
-    extern __shared__ uint32_t hot_lds[];
     LdsVis lds = LdsVis::none(hot_lds);
-    if (p.hot_words > 0 && (int64_t)sh.found >= p.hot_min_frontier) {
+    if (p.hot_words > 0 && large) {
         const unsigned long long* src = reinterpret_cast<const unsigned long long*>(p.hot_vis);
         unsigned long long* dst = reinterpret_cast<unsigned long long*>(hot_lds);
         for (int i = tid; i < p.hot_words / 2; i += BLOCK) dst[i] = ld(src + i);
         lds.set_hot((uint32_t)p.hot_span, (uint32_t)p.hot_shift);
         __syncthreads();
-    } else if (p.full_words > 0 && (int64_t)sh.found >= p.hot_min_frontier) {
+    } else if (p.full_words > 0 && large) {
         const unsigned long long* src = reinterpret_cast<const unsigned long long*>(p.vis_prev);
         unsigned long long* dst = reinterpret_cast<unsigned long long*>(hot_lds);
         for (int i = tid; i < p.full_words / 2; i += BLOCK) dst[i] = ld(src + i);
@@ -957,7 +1176,7 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl_arg) {
     }
 
     // ---- rows of degree > T2: the level's big-row arcs, split evenly
-    if (ta > 0) {
+    if (ta > 0 && !big_done) {
         int64_t per = (ta + G - 1) / G;
         if (per < p.min_share) per = p.min_share;
         const int64_t a0 = bid * per;
@@ -1420,13 +1639,52 @@ __global__ void k_symmetry(const OffT* off, const int32_t* col, int64_t n, unsig
 template <typename OffT>
 __global__ void k_relabel_cols(const OffT* off, const int32_t* col, const int64_t* noff, const int32_t* new2old,
                                const int32_t* old2new, int32_t* ncol, int64_t n, int32_t hot_span,
-                               int32_t hot_shift) {
+                               int32_t hot_shift, int32_t big_threshold, int32_t blk_shift, int32_t nblk,
+                               uint32_t* bseg) {
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t x = wave; x < n; x += waves) {
         const int64_t u = new2old[x];
         const int64_t b = (int64_t)off[u], d = (int64_t)off[u + 1] - b, nb = noff[x];
+        if (nblk > 0 && d > big_threshold) {
+            // Row above T2: columns grouped by destination block (stable),
+            // lane k < nblk counting block k; then the first arc of every
+            // block and the degree go to the row's entry (its hot rank).
+            uint32_t cnt = 0;
+            for (int64_t j0 = 0; j0 < d; j0 += 64) {
+                const int64_t j = j0 + lane;
+                const int blk = j < d ? (int)((uint32_t)old2new[col[b + j]] >> blk_shift) : -1;
+                uint64_t todo = __ballot(blk >= 0);
+                while (todo) {
+                    const int k = __shfl(blk, __builtin_ctzll(todo), 64);
+                    const uint64_t m = __ballot(blk == k);
+                    if (lane == k) cnt += (uint32_t)__popcll(m);
+                    todo &= ~m;
+                }
+            }
+            const int excl = wave_incl_scan((int)cnt, lane) - (int)cnt;
+            uint32_t rank = 0;
+            const bool hot = hot_slot((uint32_t)x, (uint32_t)hot_span, (uint32_t)hot_shift, rank);
+            if (hot && lane < nblk) bseg[(size_t)rank * (nblk + 1) + lane] = (uint32_t)excl;
+            if (hot && lane == 0) bseg[(size_t)rank * (nblk + 1) + nblk] = (uint32_t)d;  // nblk may be 64
+            int cursor = excl;  // lane k: next slot of block k
+            for (int64_t j0 = 0; j0 < d; j0 += 64) {
+                const int64_t j = j0 + lane;
+                const int32_t v = j < d ? old2new[col[b + j]] : -1;
+                const int blk = v >= 0 ? (int)((uint32_t)v >> blk_shift) : -1;
+                uint64_t todo = __ballot(blk >= 0);
+                while (todo) {
+                    const int k = __shfl(blk, __builtin_ctzll(todo), 64);
+                    const uint64_t m = __ballot(blk == k);
+                    const int at = __shfl(cursor, k, 64);
+                    if (blk == k) ncol[nb + at + rank_in(m)] = v;
+                    if (lane == k) cursor += __popcll(m);
+                    todo &= ~m;
+                }
+            }
+            continue;
+        }
         if (d <= 64) {
             // Short row: one sort across the wavefront. Hot neighbours first by
             // rank (highest degree first), then the others in arc order.
@@ -1537,8 +1795,12 @@ Grids grids_for(bfs_graph* g, const bfs_tunables& t, int64_t nslots, int lds_wor
 template <typename OffT, int BLOCK, bool kAtomic>
 void launch_typed(bfs_graph* g, const bfs_tunables& t, Workspace* w, SingleParams& p, hipStream_t s,
                   hipEvent_t stop) {
-    const int lds_words = std::max<int>(p.hot_words, p.full_words);
+    const int lds_words = std::max<int>(std::max<int>(p.hot_words, p.full_words),
+                                        p.bseg ? 1 << (p.blk_shift - 5) : 0);
     const Grids gr = grids_for<OffT, BLOCK, kAtomic>(g, t, w->nslots, lds_words);
+    // Block-by-block expansion pays off once every workgroup has a few
+    // hundred arcs of the big rows to walk.
+    p.blk_min_arcs = (int64_t)gr.expand * 256;
     const int init_grid = (int)std::min<int64_t>(std::max<int64_t>(p.n / 4, p.words) / BLOCK + 1, 4096);
     k_init<OffT, BLOCK><<<init_grid, BLOCK, 0, s>>>(p, (int)w->nslots);
     BFS_HIP(hipGetLastError());
@@ -1639,6 +1901,15 @@ void launch_single(bfs_graph* g, const bfs_tunables& t, Workspace* w, int32_t ro
     p.restore_grid = g->restore_grid;
     p.t1 = t.small_max_degree;
     p.min_share = t.chunk_arcs > 0 ? t.chunk_arcs : 1024;
+    // Destination blocks of the copy's rows above T2 (built for this T2 and
+    // block size, and fitting the LDS bitmap of the expansion workgroup).
+    const bool blocked = h && h->nblk > 0 && h->d_bseg && h->blk_req == t.block_vertices &&
+                         ((int64_t)1 << (h->blk_shift - 5)) <= lds_visited_words_max(t.block_size);
+    p.bseg = blocked ? h->d_bseg : nullptr;
+    p.bseg_rows = blocked ? h->big.num_big : 0;
+    p.nblk = blocked ? h->nblk : 0;
+    p.blk_shift = blocked ? h->blk_shift : 0;
+    p.blk_min_arcs = 0;  // set with the grid
     p.hot_words = h ? h->hot / 32 : 0;
     p.hot_shift = h ? h->shift : 5;
     p.hot_span = h ? h->span : 0;
@@ -1750,14 +2021,19 @@ bool csr_is_symmetric(const bfs_graph* g) {
 }
 
 void launch_relabel_cols(const bfs_graph* g, const int64_t* d_noff, const int32_t* d_new2old,
-                         const int32_t* d_old2new, int32_t* d_ncol, int32_t hot_span, int32_t hot_shift) {
+                         const int32_t* d_old2new, int32_t* d_ncol, int32_t hot_span, int32_t hot_shift,
+                         int32_t big_threshold, int32_t blk_shift, int32_t nblk, uint32_t* d_bseg) {
+    if (nblk > kMaxBlocks || (nblk > 0 && (!d_bseg || blk_shift < 11 || blk_shift > 20)))
+        fail(BFS_E_INTERNAL, "destination blocks out of range");
     const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((g->n + 3) / 4, (int64_t)g->cu_count * 32));
     if (g->off32)
         k_relabel_cols<int32_t><<<blocks, 256>>>(static_cast<const int32_t*>(g->d_off), g->d_col, d_noff, d_new2old,
-                                                 d_old2new, d_ncol, g->n, hot_span, hot_shift);
+                                                 d_old2new, d_ncol, g->n, hot_span, hot_shift, big_threshold,
+                                                 blk_shift, nblk, d_bseg);
     else
         k_relabel_cols<int64_t><<<blocks, 256>>>(static_cast<const int64_t*>(g->d_off), g->d_col, d_noff, d_new2old,
-                                                 d_old2new, d_ncol, g->n, hot_span, hot_shift);
+                                                 d_old2new, d_ncol, g->n, hot_span, hot_shift, big_threshold,
+                                                 blk_shift, nblk, d_bseg);
     BFS_HIP(hipGetLastError());
 }
 

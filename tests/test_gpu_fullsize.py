@@ -52,6 +52,19 @@ def test_single_root_full_scale(scale, oracle_roots, cert_roots):
     certify_runs(g, dg, roots[oracle_roots:oracle_roots + cert_roots], workers=8 if scale >= 26 else 0)
 
 
+def test_destination_blocks_rmat24():
+    """The destination-blocked expansion of the rows above T2 (off by default:
+    slower at this size) at full size: 16 blocks of 2^20 vertices, one oracle
+    root and seven certified, top-down."""
+    torch_mod()
+    g = graphgen.cached("rmat", scale=24, edgefactor=16, seed=1)
+    dg = load(g)
+    bfs.bfs_graph_set_tunables(dg, block_vertices=1 << 20)
+    roots = graphgen.pick_roots(g, 64, seed=2)
+    check_root(g, dg, int(roots[0]))
+    certify_runs(g, dg, roots[1:8])
+
+
 def test_hybrid_rmat24():
     """Direction-optimising runs at full size, in the configuration the hybrid
     bench times (degree-ordered copy on by default at this size)."""

@@ -110,6 +110,10 @@ def test_device_pointer_graph():
     dict(sparse_frontier=-1),                                   # every level through the grid kernels
     dict(sparse_frontier=1),                                    # the single-workgroup path for 1-vertex frontiers only
     dict(sparse_frontier=64, update_mode=2),
+    dict(hot_vertices=2048, block_vertices=2048),               # big rows grouped into 8 destination blocks
+    dict(hot_vertices=2048, block_vertices=2048, update_mode=2),
+    dict(hot_vertices=1024, block_vertices=4096, small_max_degree=16, wave_max_degree=64),
+    dict(hot_vertices=512, block_vertices=-1),                  # copy without destination blocks
 ])
 def test_bins_and_launch_shapes(tun):
     """Correctness does not depend on the degree bins or the launch shape."""
@@ -118,6 +122,27 @@ def test_bins_and_launch_shapes(tun):
     bfs.bfs_graph_set_tunables(dg, **tun)
     for r in graphgen.pick_roots(g, 3, seed=8):
         check_root(g, dg, int(r))
+
+
+@pytest.mark.parametrize("scale,blk,flags", [
+    (16, 2048, 0),                  # 32 destination blocks
+    (16, 2048, bfs.BFS_HYBRID),
+    (17, 2048, 0),                  # 64 blocks, the most a row may span
+    (18, 2048, 0),                  # 128 blocks: no grouping, the general path
+    (17, 1 << 20, 0),               # one block holding every vertex
+])
+def test_destination_blocks(scale, blk, flags):
+    """Rows above T2 on the degree-ordered copy grouped by destination block and
+    expanded block by block (each workgroup holding one block's visited bits in
+    LDS) at the large levels: levels exact, parents valid, statistics equal to
+    the oracle's, top-down and direction-optimising."""
+    g = graphgen.rmat(scale, 16, seed=79)
+    dg = load(g, symmetric=True)
+    bfs.bfs_graph_set_tunables(dg, hot_vertices=4096, block_vertices=blk, block_size=1024, wave_max_degree=128)
+    assert bfs.bfs_graph_get_tunables(dg)["block_vertices"] == blk
+    for r in graphgen.pick_roots(g, 4, seed=80):
+        check_root(g, dg, int(r), flags=flags)
+    bfs.bfs_graph_free(dg)
 
 
 def test_erdos_renyi():

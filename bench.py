@@ -339,6 +339,13 @@ def batch_case(args, name: str, widths, steps: int):
     for b in widths:
         lv = torch.empty((b, g.n), dtype=torch.int32, device="cuda")
         pa = torch.empty((b, g.n), dtype=torch.int32, device="cuda")
+        # The other launch form first (per-level launches when the default is
+        # one persistent launch, or the reverse), for comparison only.
+        form = bfs.bfs_graph_get_tunables(dg)["persistent"]
+        bfs.bfs_graph_set_tunables(dg, persistent=-form)
+        bfs.bfs_run_batch(dg, pool[:b], lv, pa)
+        t_other = sum(bfs.bfs_run_batch(dg, pool[:b], lv, pa)["device_ms"] for _ in range(steps)) / steps
+        bfs.bfs_graph_set_tunables(dg, persistent=form)
         bfs.bfs_run_batch(dg, pool[:b], lv, pa)  # warm-up
         sts = [bfs.bfs_run_batch(dg, pool[:b], lv, pa) for _ in range(steps)]
         t_ms = sum(st["device_ms"] for st in sts) / len(sts)
@@ -355,7 +362,9 @@ def batch_case(args, name: str, widths, steps: int):
                "one_at_a_time_gteps": round(m_sum / (t_single * 1e-3) / 1e9, 2),
                "levels": st["num_levels"], "active_rows": rows, "active_row_arcs": row_arcs,
                "bytes_alg": b_alg, "achieved_gbs": round(achieved, 1),
-               "frac": round(achieved / HBM_PEAK_GBS, 4), "runs": len(sts)}
+               "frac": round(achieved / HBM_PEAK_GBS, 4), "runs": len(sts),
+               "launch": "one cooperative launch for all levels" if form > 0 else "one launch per kernel and level",
+               "other_launch_form_ms": round(t_other, 3)}
         rec["speedup"] = round(rec["batch_gteps"] / rec["one_at_a_time_gteps"], 2)
         results.append(rec)
         print(f"[bench] {rec}", file=sys.stderr, flush=True)
@@ -376,7 +385,7 @@ def bench_batch(args) -> int:
                                                        "(64 roots) and Erdos-Renyi 2^22 avg degree 16 (8/32/64 roots)"},
            "roofline": {"bound": "hbm", "achieved": head["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": head["frac"], "traffic": None,
-                        "kernel": "bfs_run_batch (k_ms_push / k_ms_pull / k_ms_finish per level), R-MAT 22, 64 roots",
+                        "kernel": f"bfs_run_batch ({head['launch']}), R-MAT 22, 64 roots",
                         "bytes_alg_per_launch": head["bytes_alg"]},
            "cases": results}
     print(json.dumps(out), flush=True)

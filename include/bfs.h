@@ -137,12 +137,20 @@ typedef struct {
                                    for them); -1 = off, 0 = library default (off: slower
                                    at R-MAT scale 24, where a row's arcs split into short
                                    per-block runs) */
+    int32_t persistent;         /* bfs_run_batch: 1 = every level of a group in one cooperative
+                                   launch (grid-wide barriers between a level's expansion and its
+                                   finish pass, the loop ending on the device at the first empty
+                                   frontier); -1 = one launch per kernel and level, with a host
+                                   check between chunks of levels; 0 = library default (-1:
+                                   the cooperative kernel holds fewer waves per CU and is slower) */
 } bfs_tunables;
 
 /* ---- graph residency ------------------------------------------------------ */
 
 /*
- * Make a CSR graph resident on the current HIP device.
+ * Make a CSR graph resident on the current HIP device. The graph is the
+ * adjacency structure of section 3.3.1: row offsets and a column array of
+ * neighbour ids (compressed sparse rows), which every later call reads.
  *   n        number of vertices, 1 <= n <= 2^31-1.
  *   nnz      number of arcs (directed CSR entries), 0 <= nnz <= 2^32 - 1.
  *   offsets  int64_t[n+1] (int32_t[n+1] with BFS_LOAD_OFFSETS_I32): row v is
@@ -231,10 +239,12 @@ int bfs_run_noalloc(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parent
 /* ---- batched multi-source BFS --------------------------------------------------- */
 
 /*
- * Independent BFS from each of num_roots roots, computed together: one
- * persistent launch per group of up to 64 roots, every vertex carrying a 64-bit
- * visited / frontier mask (bit i = root i of the group). Results are exactly
- * those of num_roots separate bfs_run calls (levels identical, parents valid).
+ * Independent BFS from each of num_roots roots, computed together: each root
+ * follows the layer-by-layer procedure of section 3.1, Algorithm 1 (the
+ * outputs are defined exactly as for bfs_run), and a group of up to 64 roots
+ * shares one pass over each row, every vertex carrying a 64-bit visited /
+ * frontier mask (bit i = root i of the group). Results are exactly those of
+ * num_roots separate bfs_run calls (levels identical, parents valid).
  *   roots    host int32_t[num_roots]; duplicates allowed.
  *   levels   int32_t[num_roots * n], row-major: root i's levels at [i*n, (i+1)*n).
  *   parents  int32_t[num_roots * n], same layout.

@@ -140,7 +140,8 @@ void autotune(bfs_graph* g, const int32_t* roots, int32_t num_roots, int32_t mod
                                             lds_visited_words_max(1024)}))
             axes.insert(axes.begin() + 2, Axis{&bfs_tunables::lds_visited, {-1, 1}});
     } else {
-        axes = {{&bfs_tunables::batch_width, {16, 32, 64}},
+        axes = {{&bfs_tunables::persistent, {1, -1}},
+                {&bfs_tunables::batch_width, {16, 32, 64}},
                 {&bfs_tunables::wave_max_degree, {128, 256, 1024}},
                 {&bfs_tunables::small_max_degree, {16, 32, 64}},
                 {&bfs_tunables::blocks_per_cu, {0, 2, 4}}};

@@ -280,9 +280,13 @@ void apply_tunables(bfs_graph* g, const bfs_tunables& r) {
     if (g->ws_out > 0) fail(BFS_E_BUSY, "a run on this graph is in progress");
     const int32_t want_hot = hot_count(g, r);
     const bool big_stale = r.wave_max_degree != g->big.threshold;
-    const bool hot_stale = want_hot != (g->hot ? g->hot->hot : 0) ||
-                           (g->hot && (g->hot->big.threshold != r.wave_max_degree ||
-                                       g->hot->blk_req != r.block_vertices));
+    // The copy is rebuilt whole when its hot set or destination blocks change,
+    // and when T2 changes while its rows above T2 are grouped by block (they
+    // are grouped at build time); otherwise a new T2 only rebuilds its big-row table.
+    const bool copy_stale = want_hot != (g->hot ? g->hot->hot : 0) ||
+                            (g->hot && (g->hot->blk_req != r.block_vertices ||
+                                        (g->hot->blk_req > 0 && g->hot->big.threshold != r.wave_max_degree)));
+    const bool hot_stale = copy_stale || (g->hot && g->hot->big.threshold != r.wave_max_degree);
     if (big_stale || hot_stale) {
         // Tables are shared by every run on the graph: rebuild them only after
         // in-flight asynchronous work has drained. Workspaces hold lists sized
@@ -297,9 +301,16 @@ void apply_tunables(bfs_graph* g, const bfs_tunables& r) {
                             &g->max_degree);
             g->device_bytes += g->big.bytes;
         }
-        // The copy's rows above T2 are grouped by destination block: a new T2
-        // or block size regroups them, so the copy is rebuilt whole.
-        if (hot_stale) build_hot_layout(g, want_hot, r.wave_max_degree, r.block_vertices);
+        if (copy_stale) {
+            build_hot_layout(g, want_hot, r.wave_max_degree, r.block_vertices);
+        } else if (g->hot && g->hot->big.threshold != r.wave_max_degree) {
+            HotLayout& h = *g->hot;
+            g->device_bytes -= h.big.bytes;
+            h.bytes -= h.big.bytes;
+            build_big_table(h.big, h.d_off, false, g->n, r.wave_max_degree, g->restore_grid, g->cu_count, nullptr);
+            g->device_bytes += h.big.bytes;
+            h.bytes += h.big.bytes;
+        }
     }
     g->tun = r;
 }
@@ -337,6 +348,9 @@ bfs_tunables default_tunables(const bfs_graph* g) {
     // Destination-blocked expansion of the rows above T2: measured slower at
     // R-MAT scale 24 (the rows' arcs split into short per-block runs), so off.
     t.block_vertices = -1;
+    // One cooperative launch per batch is measured slower than per-level
+    // launches (R-MAT 22, 64 roots: 11.45 ms against 10.16 ms), so off.
+    t.persistent = -1;
     if (fits) t.block_size = 1024;
     return t;
 }
@@ -363,6 +377,8 @@ bfs_tunables resolve_tunables(const bfs_graph* g, const bfs_tunables& in) {
     if (t.hot_vertices == 0) t.hot_vertices = d.hot_vertices;
     if (t.hot_vertices < 0) t.hot_vertices = -1;
     if (t.hot_vertices > kMaxHotWords * 32) t.hot_vertices = kMaxHotWords * 32;
+    if (t.persistent == 0) t.persistent = d.persistent;
+    t.persistent = t.persistent > 0 ? 1 : -1;
     if (t.block_vertices == 0) t.block_vertices = d.block_vertices;
     if (t.block_vertices < 0) {
         t.block_vertices = -1;

@@ -22,6 +22,7 @@
 // the server, accumulates per-slot totals. Every statistic is striped over
 // separate cache lines; the next level's kernels read the stripes and agree on
 // the direction and on termination without host involvement.
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -261,33 +262,36 @@ struct PushShared {
     int big_first;
 };
 
-template <typename OffT, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_ms_push(MsParams p, int lvl) {
-    constexpr int NW = BLOCK / 64;
-    __shared__ PushShared<BLOCK> sh;
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int64_t G = gridDim.x, bid = blockIdx.x;
-    if (ld(&p.ctrl->done)) return;
+// Start of level lvl, by every workgroup of its first kernel (or of the
+// persistent batch kernel): the level's summary; workgroup 0 clears the next
+// level's statistics and, when the frontier is empty, marks the run done.
+__device__ __forceinline__ LevelView begin_level(const MsParams& p, int lvl) {
+    const int tid = threadIdx.x;
     const LevelView lv = read_level(p.ctrl, lvl);
-    if (bid == 0 && tid < 64) {  // statistics of the next level start from zero
+    if (blockIdx.x == 0 && tid < 64) {  // statistics of the next level start from zero
         const int np = (lvl + 1) & 1;
         st(sd(p.ctrl, np, tid), 0ull);
         st(sa(p.ctrl, np, tid), 0ull);
         st(sl(p.ctrl, np, tid), 0ull);
     }
-    if (lv.disc == 0) {
-        if (bid == 0 && tid == 0) {
+    if (blockIdx.x == 0 && tid == 0) {
+        if (lv.disc == 0) {
             st(&p.ctrl->num_levels, lvl);
             st(&p.ctrl->done, 1);
+        } else {
+            st(&p.ctrl->total_disc, ld(&p.ctrl->total_disc) + lv.disc);
+            st(&p.ctrl->num_levels, lvl + 1);
         }
-        return;
     }
-    if (bid == 0 && tid == 0) {
-        st(&p.ctrl->total_disc, ld(&p.ctrl->total_disc) + lv.disc);
-        st(&p.ctrl->num_levels, lvl + 1);
-    }
-    if (!choose_push(p, lv)) return;
-    const u64 alive = lv.alive;
+    return lv;
+}
+
+// Push expansion of level lvl for the roots in `alive`, over the whole grid.
+template <typename OffT, int BLOCK>
+__device__ __forceinline__ void push_level(const MsParams& p, int lvl, u64 alive, PushShared<BLOCK>& sh) {
+    constexpr int NW = BLOCK / 64;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int64_t G = gridDim.x, bid = blockIdx.x;
 
     // Rows of degree > T2: static split of their concatenated arcs.
     if (p.num_big > 0) {
@@ -366,6 +370,15 @@ __global__ __launch_bounds__(BLOCK) void k_ms_push(MsParams p, int lvl) {
     }
 }
 
+template <typename OffT, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_ms_push(MsParams p, int lvl) {
+    __shared__ PushShared<BLOCK> sh;
+    if (ld(&p.ctrl->done)) return;
+    const LevelView lv = begin_level(p, lvl);
+    if (lv.disc == 0 || !choose_push(p, lv)) return;
+    push_level<OffT, BLOCK>(p, lvl, lv.alive, sh);
+}
+
 // ---------------------------------------------------------------------------
 // pull
 // ---------------------------------------------------------------------------
@@ -391,11 +404,7 @@ __device__ __forceinline__ u64 wave_excl_or(u64 x, int lane) {
 // whole length. A root bit found in several arcs of a step takes the lowest
 // lane's neighbour as parent.
 template <typename OffT>
-__global__ __launch_bounds__(256) void k_ms_pull(MsParams p, int lvl) {
-    if (ld(&p.ctrl->done)) return;
-    const LevelView lview = read_level(p.ctrl, lvl);
-    if (lview.disc == 0 || choose_push(p, lview)) return;
-    const u64 alive = lview.alive;
+__device__ __forceinline__ void pull_level(const MsParams& p, int lvl, u64 alive) {
     const int lane = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
@@ -468,15 +477,20 @@ __global__ __launch_bounds__(256) void k_ms_pull(MsParams p, int lvl) {
     }
 }
 
+template <typename OffT>
+__global__ __launch_bounds__(256) void k_ms_pull(MsParams p, int lvl) {
+    if (ld(&p.ctrl->done)) return;
+    const LevelView lview = read_level(p.ctrl, lvl);
+    if (lview.disc == 0 || choose_push(p, lview)) return;
+    pull_level<OffT>(p, lvl, lview.alive);
+}
+
 // ---------------------------------------------------------------------------
 // finish: statistics of the next frontier, clear the consumed frontier
 // ---------------------------------------------------------------------------
 
 template <typename OffT, bool kPerSlot>
-__global__ __launch_bounds__(256) void k_ms_finish(MsParams p, int lvl) {
-    __shared__ u64 red[4][4];
-    __shared__ u64 slot_r[64], slot_a[64];
-    if (ld(&p.ctrl->done)) return;
+__device__ __forceinline__ void finish_level(const MsParams& p, int lvl, u64 (&red)[4][4], u64* slot_r, u64* slot_a) {
     const int tid = threadIdx.x;
     if (kPerSlot) {
         if (tid < 64) {
@@ -539,6 +553,40 @@ __global__ __launch_bounds__(256) void k_ms_finish(MsParams p, int lvl) {
     if (kPerSlot && tid < 64) {
         if (slot_r[tid]) atomicAdd(&p.ctrl->slot_reached[tid], slot_r[tid]);
         if (slot_a[tid]) atomicAdd(&p.ctrl->slot_arcs[tid], slot_a[tid]);
+    }
+}
+
+template <typename OffT, bool kPerSlot>
+__global__ __launch_bounds__(256) void k_ms_finish(MsParams p, int lvl) {
+    __shared__ u64 red[4][4];
+    __shared__ u64 slot_r[64], slot_a[64];
+    if (ld(&p.ctrl->done)) return;
+    finish_level<OffT, kPerSlot>(p, lvl, red, slot_r, slot_a);
+}
+
+// A whole batch in one cooperative launch (tunable persistent): every level's expansion (push or
+// pull, chosen from the level summary that every workgroup reads alike) and
+// its finish pass, separated by grid-wide barriers; the loop ends at the
+// first empty frontier, the same level for every workgroup. The grid must be
+// co-resident (the cooperative launch checks it), so no barrier waits for a
+// workgroup that has not started.
+template <typename OffT>
+__global__ __launch_bounds__(256) void k_ms_batch(MsParams p, u64* fr0, u64* fr1, int max_levels) {
+    __shared__ PushShared<256> sh;
+    __shared__ u64 red[4][4];
+    cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+    for (int lvl = 0; lvl < max_levels; ++lvl) {
+        p.fr = (lvl & 1) ? fr1 : fr0;
+        p.nfr = (lvl & 1) ? fr0 : fr1;
+        const LevelView lv = begin_level(p, lvl);
+        if (lv.disc == 0) break;  // the same summary in every workgroup
+        if (choose_push(p, lv))
+            push_level<OffT, 256>(p, lvl, lv.alive, sh);
+        else
+            pull_level<OffT>(p, lvl, lv.alive);
+        grid.sync();
+        finish_level<OffT, false>(p, lvl, red, nullptr, nullptr);
+        grid.sync();
     }
 }
 
@@ -651,6 +699,27 @@ void enqueue_level(bfs_graph* g, const bfs_tunables& t, MsWorkspace* w, int lvl,
     BFS_HIP(hipGetLastError());
 }
 
+// One cooperative launch of the persistent batch kernel: at most
+// (occupancy - 1) workgroups per CU (one fewer than the occupancy query
+// reports is what stays resident on gfx950), fewer with blocks_per_cu; the
+// cooperative launch refuses a grid that cannot be co-resident.
+template <typename OffT>
+void launch_batch_persistent(bfs_graph* g, const bfs_tunables& t, MsWorkspace* w, hipStream_t s) {
+    if (g->big.threshold != t.wave_max_degree) fail(BFS_E_INTERNAL, "big-row table out of date");
+    MsParams p = make_params(g, t, w, 0);
+    static const int occ = occupancy_of(k_ms_batch<OffT>, 256);
+    const int fit = occ > 1 ? occ - 1 : 1;
+    const int bpc = t.blocks_per_cu > 0 && t.blocks_per_cu < fit ? t.blocks_per_cu : fit;
+    const int grid = bpc * g->cu_count;
+    if (grid < 1 || grid > occ * g->cu_count) fail(BFS_E_INTERNAL, "persistent grid larger than the resident set");
+    int max_levels = (int)std::min<int64_t>(g->n + 1, (int64_t)INT32_MAX);
+    unsigned long long* fr0 = w->fr[0];
+    unsigned long long* fr1 = w->fr[1];
+    void* args[] = {&p, &fr0, &fr1, &max_levels};
+    BFS_HIP(hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_ms_batch<OffT>), dim3(grid), dim3(256), args,
+                                       0, s));
+}
+
 void enqueue_level_any(bfs_graph* g, const bfs_tunables& t, MsWorkspace* w, int lvl, bool per_slot, hipStream_t s) {
     if (g->off32)
         enqueue_level<int32_t>(g, t, w, lvl, per_slot, s);
@@ -743,6 +812,21 @@ void ms_run_batch(bfs_graph* g, const bfs_tunables& t, MsWorkspace* w, const int
     int32_t slots[64];
     for (int i = 0; i < count; ++i) slots[i] = i;
     ms_join(g, w, slots, roots, count, 0, s, nullptr);
+    if (t.persistent > 0) {
+        // Every level in one launch; then the totals for the caller.
+        if (g->off32)
+            launch_batch_persistent<int32_t>(g, t, w, s);
+        else
+            launch_batch_persistent<int64_t>(g, t, w, s);
+        k_ms_summary<<<1, 64, 0, s>>>(w->ctrl, 0);
+        BFS_HIP(hipGetLastError());
+        BFS_HIP(hipMemcpyAsync(hc, w->ctrl, sizeof(MsCtrl), hipMemcpyDeviceToHost, s));
+        BFS_HIP(hipStreamSynchronize(s));
+        if (!hc->done) fail(BFS_E_INTERNAL, "batch ended without an empty frontier");
+        return;
+    }
+    // Per-level launches, enqueued in chunks; the host reads the done flag
+    // between chunks.
     int lvl = 0;
     int chunk = 8;
     while (true) {

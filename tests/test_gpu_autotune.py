@@ -18,7 +18,8 @@ def test_autotune_single_and_batch(tmp_path, monkeypatch):
     dg = load(g)
     roots = graphgen.pick_roots(g, 8, seed=52)
     best = tune.tuned(dg, roots[:4], "rmat", mode=0)
-    assert best["update_mode"] in (1, 2) and best["block_size"] in (256, 512)
+    assert best["update_mode"] in (1, 2) and best["block_size"] in (256, 512, 1024)
+    assert best == bfs.bfs_graph_get_tunables(dg)  # the winner is applied to the graph
     for r in roots[4:]:
         check_root(g, dg, int(r))
     again = tune.tuned(dg, roots[:4], "rmat", mode=0)  # cache hit

@@ -130,3 +130,26 @@ def test_pull_long_rows():
     check_batch(broom, load(broom), [1, 2, 3, 4999, 4998, 2500, 3500, 0, 5999])
     g = graphgen.rmat(16, 16, seed=39)
     check_batch(g, load(g), graphgen.pick_roots(g, 64, seed=40))
+
+
+@pytest.mark.parametrize("persistent", [1, -1])
+@pytest.mark.parametrize("case", ["rmat14", "path", "widths"])
+def test_persistent_and_per_level_launches(persistent, case):
+    """Both launch forms of a batch: one cooperative launch running every level
+    behind grid barriers, and one launch per kernel and level (the default).
+    Levels identical to the oracle, parents valid, totals equal; a deep graph
+    (a 3000-vertex path: 3000 levels in one launch) and uneven widths."""
+    if case == "rmat14":
+        g = graphgen.rmat(14, 16, seed=91)
+        roots = graphgen.pick_roots(g, 64, seed=92)
+    elif case == "path":
+        g = graphgen.disjoint(graphgen.path(3000), graphgen.star(50))
+        roots = [0, 1500, 2999, 3000, 3010]
+    else:
+        g = graphgen.er(1 << 13, 6, seed=93)
+        roots = np.resize(graphgen.pick_roots(g, 40, seed=94), 97)
+    dg = load(g)
+    bfs.bfs_graph_set_tunables(dg, persistent=persistent)
+    assert bfs.bfs_graph_get_tunables(dg)["persistent"] == persistent
+    check_batch(g, dg, roots)
+    bfs.bfs_graph_free(dg)

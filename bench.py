@@ -41,6 +41,29 @@ def algorithmic_bytes(n: int, reached: int, arcs: int, levels: int, off_bytes: i
     return 8 * n + 8 * reached + 2 * off_bytes * reached + 4 * arcs + levels * 3 * (n // 8)
 
 
+def hybrid_algorithmic_bytes(lv, deg, off_bytes: int) -> int:
+    """Compulsory traffic of one direction-optimising BFS, from its level array
+    (torch int32 [n] on the device) and the degrees: init 8n, level+parent
+    writes 8R, three bitmap passes per level (3 * n/8), and per level the
+    cheaper of the two directions' compulsory reads: top-down, two offsets per
+    frontier vertex and every arc of its row; bottom-up, two offsets per
+    unvisited vertex with arcs, one arc for each one found at this level and
+    every arc of each one that stays unvisited. A lower bound for any choice
+    of directions."""
+    n = lv.numel()
+    L = int(lv.max().item()) + 1
+    has = deg > 0
+    total = 8 * n + 8 * int((lv >= 0).sum().item()) + L * 3 * (n // 8)
+    for k in range(L):
+        fr = lv == k
+        td = 2 * off_bytes * int(fr.sum().item()) + 4 * int(deg[fr].sum().item())
+        unv = ((lv > k) | (lv < 0)) & has
+        disc = lv == k + 1
+        bu = 2 * off_bytes * int(unv.sum().item()) + 4 * (int(disc.sum().item()) + int(deg[unv & ~disc].sum().item()))
+        total += min(td, bu)
+    return total
+
+
 def batch_algorithmic_bytes(n: int, roots: int, levels: int, rows: int, row_arcs: int, discovered: int,
                             off_bytes: int) -> int:
     """Compulsory traffic of one multi-source run of `roots` roots: per level a
@@ -115,11 +138,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="leave the R-MAT 22 batched object out of the line")
     ap.add_argument("--tune", action="store_true", help="run the autotuner on 4 roots first")
+    ap.add_argument("--no-shipped-tunables", action="store_true",
+                    help="library defaults instead of the shipped autotuner result for this configuration")
     ap.add_argument("--tunables", default="", help='JSON object of bfs_tunables fields, e.g. {"update_mode": 2}')
     ap.add_argument("--details", default="", help="write per-root records (JSON) to this path")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="also run a plain copy kernel of BYTES (read and written) for counter scaling")
-    ap.add_argument("--mode", default="single", choices=["single", "batch", "serve"])
+    ap.add_argument("--mode", default="single", choices=["single", "batch", "serve", "ceilings"])
     ap.add_argument("--rates", default="1000,5000,10000,20000,50000", help="serve: arrival rates (queries/s)")
     ap.add_argument("--queries", type=int, default=4000, help="serve: queries per rate")
     ap.add_argument("--warmup-queries", type=int, default=400, help="serve: leading queries left out of the stats")
@@ -147,6 +172,8 @@ def main() -> int:
     bfs.load_library()
     if args.mode == "batch":
         return bench_batch(args)
+    if args.mode == "ceilings":
+        return bench_ceilings(args)
     if args.mode == "serve":
         return bench_serve(args)
 
@@ -159,6 +186,12 @@ def main() -> int:
     dg = bfs.bfs_graph_load_csr(g.offsets_i32() if args.offsets_i32 else g.offsets, g.cols,
                                 bfs.BFS_LOAD_SYMMETRIC if args.hybrid else 0)
     run_flags = bfs.BFS_HYBRID if args.hybrid else 0
+    # The autotuner's choice for this configuration, when one is shipped.
+    from paper_1604_02844_amd import tune
+
+    shipped = None if args.no_shipped_tunables else tune.apply_shipped(dg, "rmat", 0)
+    if shipped:
+        print(f"[bench] shipped autotuner tunables {shipped['key']}", file=sys.stderr, flush=True)
     if args.tunables:
         bfs.bfs_graph_set_tunables(dg, **json.loads(args.tunables))
     if args.tune:
@@ -198,6 +231,15 @@ def main() -> int:
     wall = time.perf_counter() - t0
 
     off_bytes = 4 if args.offsets_i32 else 8
+    hyb_bytes = {}
+    if args.hybrid:
+        # Direction-optimising runs: bytes from each root's levels (an untimed
+        # rerun after the timed region; levels are the same every run).
+        deg = torch.from_numpy(np.diff(g.offsets)).to(dev)
+        for r in roots:
+            bfs.bfs_run(dg, int(r), lv, pa, stream=stream, flags=run_flags)
+            hyb_bytes[int(r)] = hybrid_algorithmic_bytes(lv, deg, off_bytes)
+        del deg
     inv_teps = 0.0
     bytes_total = 0
     ms_total = 0.0
@@ -206,7 +248,8 @@ def main() -> int:
         t = st["device_ms"] * 1e-3
         m = st["edges_traversed"]
         inv_teps += t / m if m > 0 else float("inf")
-        b = algorithmic_bytes(g.n, st["reached"], st["arcs_scanned"], st["num_levels"], off_bytes)
+        b = hyb_bytes[r] if args.hybrid else algorithmic_bytes(g.n, st["reached"], st["arcs_scanned"],
+                                                                 st["num_levels"], off_bytes)
         bytes_total += b
         ms_total += st["device_ms"]
         per_root.append({"root": r, "ms": st["device_ms"], "m": m, "reached": st["reached"],
@@ -273,13 +316,16 @@ def main() -> int:
                                f"A/B/C/D=.57/.19/.19/.05, permuted, symmetrised, deduplicated, int32 cols, "
                                f"int{off_bytes * 8} offsets, {len(roots)} seeded roots of degree>0",
                    "n": g.n, "nnz": g.nnz, "roots": len(roots), "step": f"{len(roots)} BFS runs",
-                   "tunables": bfs.bfs_graph_get_tunables(dg)},
+                   "tunables": bfs.bfs_graph_get_tunables(dg),
+                   "tunables_from": ("autotuner, shipped cache " + shipped["key"]) if shipped and not args.tunables
+                   else ("--tunables" if args.tunables else "library defaults")},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "bfs_run: k_init, k_expand + k_restore per level, k_out on the degree-ordered copy",
                      "avg_launch_ms": round(avg_ms, 4), "bytes_alg_per_launch": int(bytes_total / launches),
                      "workload_key": workload_key,
-                     **({"note": "bytes follow the top-down definition; bottom-up levels read fewer columns"}
+                     **({"bytes_model": "per level, the cheaper direction's compulsory reads (a lower bound "
+                                        "for any choice of directions); see hybrid_algorithmic_bytes"}
                         if args.hybrid else {})},
         "cpu_baseline": cpu,
     }
@@ -327,6 +373,9 @@ def batch_case(args, name: str, widths, steps: int):
     widths = [widths] if one else list(widths)
     g = _batch_graph(name, args.seed)
     dg = bfs.bfs_graph_load_csr(g.offsets, g.cols)
+    from paper_1604_02844_amd import tune
+
+    shipped = None if args.no_shipped_tunables else tune.apply_shipped(dg, "rmat" if name.startswith("rmat") else "er", 1)
     deg = torch.from_numpy(np.diff(g.offsets)).cuda()
     pool = graphgen.pick_roots(g, max(widths), seed=args.root_seed)
     lv1 = torch.empty(g.n, dtype=torch.int32, device="cuda")
@@ -364,6 +413,7 @@ def batch_case(args, name: str, widths, steps: int):
                "bytes_alg": b_alg, "achieved_gbs": round(achieved, 1),
                "frac": round(achieved / HBM_PEAK_GBS, 4), "runs": len(sts),
                "launch": "one cooperative launch for all levels" if form > 0 else "one launch per kernel and level",
+               "tunables_from": ("autotuner, shipped cache " + shipped["key"]) if shipped else "library defaults",
                "other_launch_form_ms": round(t_other, 3)}
         rec["speedup"] = round(rec["batch_gteps"] / rec["one_at_a_time_gteps"], 2)
         results.append(rec)
@@ -424,6 +474,57 @@ def _trace(graphs, rate, count, seed):
     pick = graphgen.uniform_u64(seed + 2, 50 + int(rate) % 997, count, 1 << 62)
     roots = np.array([pools[c][int(pick[i] % len(pools[c]))] for i, c in enumerate(choice)], dtype=np.int64)
     return arrivals, choice, roots
+
+
+def bench_ceilings(args) -> int:
+    """Memory-system ceilings (libceilings.so): streaming read and copy of 1 GiB,
+    random 4-byte gathers from tables of 128 KiB to 128 MiB (8 gathers in flight
+    per thread), random device-scope atomicOr without a returned value into a
+    2 MiB table, and back-to-back empty launches. One JSON line."""
+    import ctypes
+
+    import torch
+
+    lib = ctypes.CDLL(os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1604_02844_amd",
+                                   "libceilings.so"))
+    i64, i32, vp, pf = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_float)
+    lib.ceil_read.argtypes = [vp, i64, vp, i32, pf]
+    lib.ceil_copy.argtypes = [vp, vp, i64, i32, pf]
+    lib.ceil_gather.argtypes = [vp, i64, i64, vp, i32, pf]
+    lib.ceil_atomic_or.argtypes = [vp, i64, i64, i32, pf]
+    lib.ceil_empty.argtypes = [i32, pf]
+    ms = ctypes.c_float()
+
+    def call(fn, *a):
+        rc = fn(*a, ctypes.byref(ms))
+        if rc != 0:
+            raise RuntimeError(f"{fn.__name__} returned {rc}")
+        return ms.value
+
+    gib = 1 << 30
+    src = torch.ones(gib // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    out = {"metric": "memory-system ceilings", "n_gpus": 1, "data": "synthetic"}
+    t = call(lib.ceil_read, src.data_ptr(), gib, sink.data_ptr(), 10)
+    out["stream_read_gbs"] = round(gib / (t * 1e-3) / 1e9, 1)
+    t = call(lib.ceil_copy, dst.data_ptr(), src.data_ptr(), gib, 10)
+    out["copy_gbs"] = round(2 * gib / (t * 1e-3) / 1e9, 1)
+    gathers = {}
+    count = 1 << 28
+    for kib in (128, 2048, 8192, 32768, 131072):
+        words = kib * 256
+        t = call(lib.ceil_gather, src.data_ptr(), words, count, sink.data_ptr(), 5)
+        gathers[f"{kib}KiB"] = round(count / (t * 1e-3) / 1e9, 1)
+    out["random_gather_g_per_s"] = gathers
+    table = torch.zeros(1 << 19, dtype=torch.int32, device="cuda")
+    count = 1 << 26
+    t = call(lib.ceil_atomic_or, table.data_ptr(), 1 << 19, count, 5)
+    out["atomic_or_2MiB_g_per_s"] = round(count / (t * 1e-3) / 1e9, 1)
+    t = call(lib.ceil_empty, 1000)
+    out["empty_launch_us"] = round(t * 1e3, 2)
+    print(json.dumps(out), flush=True)
+    return 0
 
 
 def bench_serve(args) -> int:

@@ -13,6 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libbfs.so")
+# Memory-system ceiling microbenchmarks (bench.py --mode ceilings): a library of their own.
+CEIL_LIB = os.path.join(HERE, "libceilings.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 SOURCES = ["graph.cpp", "abi.cpp", "autotune.cpp", "server.cpp", "single.hip", "multi.hip", "parents.hip", "noalloc.hip"]
 ARCH = os.environ.get("BFS_OFFLOAD_ARCH", "gfx950")
@@ -60,6 +62,11 @@ def build(force: bool = False, verbose: bool = False) -> str:
         tmp = LIB + ".tmp"
         run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"])
         os.replace(tmp, LIB)
+    ceil_src = os.path.join(CSRC, "ceilings.hip")
+    if force or _needs(CEIL_LIB, [ceil_src]):
+        tmp = CEIL_LIB + ".tmp"
+        run(["hipcc", *HIP_FLAGS, "-shared", "-x", "hip", ceil_src, "-o", tmp])
+        os.replace(tmp, CEIL_LIB)
     return LIB
 
 

@@ -143,6 +143,14 @@ typedef struct {
                                    frontier); -1 = one launch per kernel and level, with a host
                                    check between chunks of levels; 0 = library default (-1:
                                    the cooperative kernel holds fewer waves per CU and is slower) */
+    int32_t hub_bins;           /* single-root runs: at a level whose frontier is small but whose
+                                   rows above T2 carry many arcs (the level that expands the hubs),
+                                   each arc's head and parent go to a bin of its 8192-vertex
+                                   destination chunk instead of probing the global visited
+                                   bitmap; the restoration pass, which owns each chunk's visited
+                                   words, then claims the binned heads exactly in LDS. 1 = on,
+                                   -1 = off, 0 = library default (off: slower at R-MAT scale 24,
+                                   where the scattered entry stores do not combine in L2) */
 } bfs_tunables;
 
 /* ---- graph residency ------------------------------------------------------ */

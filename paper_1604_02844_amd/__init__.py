@@ -71,7 +71,8 @@ class Tunables(ctypes.Structure):
                 ("block_size", ctypes.c_int32), ("batch_width", ctypes.c_int32),
                 ("update_mode", ctypes.c_int32), ("hot_vertices", ctypes.c_int32),
                 ("lds_visited", ctypes.c_int32), ("sparse_frontier", ctypes.c_int32),
-                ("block_vertices", ctypes.c_int32), ("persistent", ctypes.c_int32)]
+                ("block_vertices", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("hub_bins", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -53,6 +53,9 @@ struct Ctrl {
     int skip_e;
     int r_ran;
     int pad2;
+    // Whether the expansion of a level (indexed by its parity) put the heads of
+    // its big-row arcs into destination bins for the restoration pass to claim.
+    int binned[2];
 };
 
 // Scratch of one single-root run.
@@ -81,6 +84,13 @@ struct Workspace {
     uint32_t* hot_fr = nullptr;     // compact frontier bitmap of the hot vertices
     int32_t hot_capacity = 0;       // its words
     int32_t* run_rec = nullptr;     // {level, parent} per degree-ordered id (runs on the copy)
+    // Destination bins of one level's big-row arcs: a bin per restore chunk
+    // (256 visited words, 8192 vertices), a region of bin_k entries per
+    // (bin, expansion workgroup); entries are {head, parent as a caller id}.
+    int2* bin_e = nullptr;
+    int64_t bin_cap = 0;            // entries
+    uint32_t* bin_cnt = nullptr;    // [workgroup][bin] entries written
+    int64_t bin_cnt_cap = 0;
     Ctrl* host_ctrl = nullptr;      // pinned mirror for stats
     int32_t* out_levels = nullptr;  // staging for BFS_OUT_HOST
     int32_t* out_parents = nullptr;
@@ -258,10 +268,13 @@ int restore_grid_for(int64_t words, int cu_count);
 // (apply_tunables refuses with BFS_E_BUSY while any workspace is out).
 Workspace* acquire_ws(bfs_graph* g, hipStream_t s, bfs_tunables* t = nullptr);
 void release_ws(bfs_graph* g, Workspace* w, hipStream_t s);
-// Bytes one single-root workspace of this graph needs (for its current tables).
-// With `base` (256-byte aligned, that many bytes) the workspace's buffers are
-// also carved from it; events and the host mirror are left to the caller.
-size_t ws_layout(const bfs_graph* g, Workspace* w, char* base);
+// Bytes one single-root workspace of this graph needs (for its current tables;
+// with `bins`, also the destination bins of hub levels). With `base` (256-byte
+// aligned, that many bytes) the workspace's buffers are also carved from it;
+// events and the host mirror are left to the caller.
+size_t ws_layout(const bfs_graph* g, Workspace* w, char* base, bool bins = true);
+// Most expansion workgroups whose bins a workspace holds counts for.
+constexpr int kMaxBinGroups = 2048;
 MsWorkspace* acquire_ms(bfs_graph* g, hipStream_t s, bfs_tunables* t = nullptr);
 void release_ms(bfs_graph* g, MsWorkspace* w, hipStream_t s);
 // The graph's resolved tunables, read under g->mu.

@@ -287,6 +287,13 @@ void apply_tunables(bfs_graph* g, const bfs_tunables& r) {
                             (g->hot && (g->hot->blk_req != r.block_vertices ||
                                         (g->hot->blk_req > 0 && g->hot->big.threshold != r.wave_max_degree)));
     const bool hot_stale = copy_stale || (g->hot && g->hot->big.threshold != r.wave_max_degree);
+    if (r.hub_bins != resolve_tunables(g, g->tun).hub_bins && !big_stale && !hot_stale) {
+        // Workspaces hold the bins only while they are on: drop them.
+        BFS_HIP(hipDeviceSynchronize());
+        for (auto* w : g->ws_all) g->device_bytes -= w->bytes;
+        for (auto* w : g->ms_all) g->device_bytes -= w->bytes;
+        free_workspaces(g);
+    }
     if (big_stale || hot_stale) {
         // Tables are shared by every run on the graph: rebuild them only after
         // in-flight asynchronous work has drained. Workspaces hold lists sized
@@ -351,6 +358,9 @@ bfs_tunables default_tunables(const bfs_graph* g) {
     // One cooperative launch per batch is measured slower than per-level
     // launches (R-MAT 22, 64 roots: 11.45 ms against 10.16 ms), so off.
     t.persistent = -1;
+    // Hub-level destination bins: exact, but slower at R-MAT scale 24 (the
+    // scattered entry stores do not combine in L2), so off.
+    t.hub_bins = -1;
     if (fits) t.block_size = 1024;
     return t;
 }
@@ -377,6 +387,8 @@ bfs_tunables resolve_tunables(const bfs_graph* g, const bfs_tunables& in) {
     if (t.hot_vertices == 0) t.hot_vertices = d.hot_vertices;
     if (t.hot_vertices < 0) t.hot_vertices = -1;
     if (t.hot_vertices > kMaxHotWords * 32) t.hot_vertices = kMaxHotWords * 32;
+    if (t.hub_bins == 0) t.hub_bins = d.hub_bins;
+    t.hub_bins = t.hub_bins > 0 ? 1 : -1;
     if (t.persistent == 0) t.persistent = d.persistent;
     t.persistent = t.persistent > 0 ? 1 : -1;
     if (t.block_vertices == 0) t.block_vertices = d.block_vertices;
@@ -395,7 +407,7 @@ bfs_tunables resolve_tunables(const bfs_graph* g, const bfs_tunables& in) {
 // stream that used it; the next user on another stream waits for that event.
 // ---------------------------------------------------------------------------
 
-size_t ws_layout(const bfs_graph* g, Workspace* w, char* base) {
+size_t ws_layout(const bfs_graph* g, Workspace* w, char* base, bool bins) {
     w->device = g->device;
     w->words = padded_words(g->n);
     w->nslots = (int64_t)g->cu_count * 64 + 64;  // >= any expansion or restore grid
@@ -408,8 +420,18 @@ size_t ws_layout(const bfs_graph* g, Workspace* w, char* base) {
     const size_t smallb = (size_t)g->restore_grid * (kSmallSeg + 1) * 4;  // listed small frontiers
     const size_t pre_rec = bmb * 3 + sizeof(Ctrl) + (size_t)w->nslots * 2 * 8 + listb + hotb + smallb;
     const size_t rec_at = (pre_rec + 255) & ~(size_t)255;
-    const size_t total = rec_at + recb;
+    // Destination bins: 4 entries per vertex (at least 2^16, at most 2^28) and
+    // one count per (bin, workgroup) for up to kMaxBinGroups workgroups.
+    const int64_t nbins = (w->words + kRestoreBlock - 1) / kRestoreBlock;
+    bins = bins && resolve_tunables(g, g->tun).hub_bins > 0;  // only graphs that use them pay for them
+    w->bin_cap = bins ? std::min<int64_t>(std::max<int64_t>(4 * g->n, (int64_t)1 << 16), (int64_t)1 << 28) : 0;
+    w->bin_cnt_cap = bins ? nbins * kMaxBinGroups : 0;
+    const size_t bin_at = (rec_at + recb + 255) & ~(size_t)255;
+    const size_t cnt_at = bin_at + (size_t)w->bin_cap * 8;
+    const size_t total = cnt_at + (size_t)w->bin_cnt_cap * 4;
     if (!base) return total;
+    w->bin_e = bins ? reinterpret_cast<int2*>(base + bin_at) : nullptr;
+    w->bin_cnt = bins ? reinterpret_cast<uint32_t*>(base + cnt_at) : nullptr;
     w->vis = reinterpret_cast<uint32_t*>(base);
     w->vis_prev = w->vis + w->words;
     w->fr = w->vis_prev + w->words;

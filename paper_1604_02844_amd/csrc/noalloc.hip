@@ -59,12 +59,12 @@ void run_noalloc(bfs_graph* g, int32_t root, int32_t* levels, int32_t* parents, 
     {
         std::lock_guard<std::mutex> lk(g->mu);
         t = resolve_tunables(g, g->tun);
-        if (ws_layout(g, &w, nullptr) > kScratchBytes)
+        if (ws_layout(g, &w, nullptr, false) > kScratchBytes)
             fail(BFS_E_NO_MEMORY, "the run needs more scratch than the static array holds");
         ++g->ws_out;
     }
     RunHold hold(g);
-    ws_layout(g, &w, static_cast<char*>(d.ptr));
+    ws_layout(g, &w, static_cast<char*>(d.ptr), false);
     w.host_ctrl = &d.host;
     w.last_launches = d.last_launches;
     // The array keeps the previous call's contents: the control block starts

@@ -56,6 +56,10 @@ namespace {
 constexpr int kUnroll = 2;     // arcs per lane in flight: one wavefront per row (T1 < d <= T2)
 constexpr int kLbsUnroll = 8;  // arcs per lane in flight: packed rows (d <= T1)
 constexpr int kBigUnroll = 8;  // arcs per lane in flight: rows above T2
+// What a walk over staged big-row arcs does with each arc.
+constexpr int kWalkProbe = 0;    // probe, confirm and claim (visit_arcs)
+constexpr int kWalkBlocked = 1;  // heads in the LDS block slice (visit_blocked)
+constexpr int kWalkBinned = 2;   // to the destination bins (visit_binned)
 constexpr int kBuFirst = 4;       // bottom-up: arcs each lane checks before its wavefront helps
 constexpr int kSmallBlock = 1024;  // threads of the small-level kernel
 constexpr int kRebuildPairs = 8;   // restore: pairs of touched words whose levels are read per round
@@ -95,6 +99,15 @@ struct SingleParams {
     // blocks of 2^blk_shift vertices; bseg holds nblk + 1 local arc offsets per
     // row, by hot rank (nullptr: not grouped). Levels whose big rows have at
     // least blk_min_arcs arcs and whose frontier is large expand them by block.
+    // Destination bins of hub levels: bin_e holds {head, parent} entries in a
+    // region of bin_k per (bin, expansion workgroup), bin_cnt[workgroup][bin]
+    // the entries each region got; a bin is a restore chunk (kRestoreBlock
+    // visited words). bin_k 0 = off.
+    int2* bin_e;
+    uint32_t* bin_cnt;
+    int32_t bin_k;
+    int32_t bin_groups;        // expansion workgroups (regions per bin)
+    int32_t bin_nb;            // bins
     const uint32_t* bseg;
     int32_t bseg_rows;         // rows in bseg
     int32_t nblk;
@@ -215,6 +228,22 @@ __device__ __forceinline__ void record(const SingleParams& p, int32_t v, int lvl
         p.out_pa[v] = par;
     }
 }
+
+// The same discovery written with device-scope stores, for a pass that reads
+// the level array back with device-scope loads in the same launch.
+__device__ __forceinline__ void record_st(const SingleParams& p, int32_t v, int lvl, int32_t par) {
+    if (p.new2old) {
+        st(reinterpret_cast<unsigned long long*>(p.lv + 2 * (int64_t)v),
+           ((unsigned long long)(uint32_t)par << 32) | (uint32_t)lvl);
+    } else {
+        st(p.lv + v, lvl);
+        st(p.out_pa + v, par);
+    }
+}
+
+// Bins are restore chunks: kRestoreBlock visited words of 32 vertices.
+static_assert(kRestoreBlock == 256, "a bin is 256 visited words (8192 vertices)");
+constexpr int kBinShift = 13;
 
 // Compact-bitmap slot of v if v is hot: position k = (v & 31) >> shift of
 // visited word w = v >> 5 < span has slot w + k * span.
@@ -603,6 +632,34 @@ __device__ __forceinline__ void visit_blocked(const SingleParams& p, const int64
     }
 }
 
+// Visit of arcs at a hub level: each head goes, with its parent, to the bin
+// of its restore chunk, in this workgroup's region of that bin (position from
+// the workgroup's LDS counter); the restoration pass claims them. A region
+// that is full sends further heads down the general claim path.
+template <bool kAtomic, int U>
+__device__ __forceinline__ void visit_binned(const SingleParams& p, const int64_t (&pos)[U], const bool (&ok)[U],
+                                             const int32_t (&par)[U], int lvl, uint32_t* cnt, uint32_t wg) {
+    int32_t v[U];
+#pragma unroll
+    for (int i = 0; i < U; ++i) v[i] = __builtin_nontemporal_load(p.col + pos[i]);
+    bool over[U], any_over = false;
+#pragma unroll
+    for (int i = 0; i < U; ++i) {
+        over[i] = false;
+        if (ok[i]) {
+            const uint32_t b = (uint32_t)v[i] >> kBinShift;
+            const uint32_t q = atomicAdd(cnt + b, 1u);
+            if (q < (uint32_t)p.bin_k) {
+                p.bin_e[((int64_t)b * p.bin_groups + wg) * p.bin_k + q] = make_int2(v[i], par[i]);
+            } else {
+                over[i] = true;
+                any_over = true;
+            }
+        }
+    }
+    if (__ballot(any_over)) visit_out<kAtomic, U>(p, v, over, par, lvl);
+}
+
 // Wavefront walk over staged rows: arcs [from, hi_arc) of a numbering in which
 // staged row r starts at sh.x.big.start[r] (non-decreasing; empty rows share
 // their successor's start) and its arc a sits at column index base[r] + a.
@@ -611,7 +668,7 @@ __device__ __forceinline__ void visit_blocked(const SingleParams& p, const int64
 // from one LDS read per lane (the next 64 staged starts) and a ballot; rows
 // are long, so a step crosses at most a few, and no lane runs a search or a
 // loop of its own.
-template <bool kAtomic, int BLOCK, bool kBlocked>
+template <bool kAtomic, int BLOCK, int kMode>
 __device__ __forceinline__ void walk_staged(const SingleParams& p, ExpandShared<BLOCK>& sh, int64_t from,
                                             int64_t hi_arc, int nt, int lvl, const LdsVis& lds, uint32_t* bits,
                                             uint32_t w0, uint32_t nw) {
@@ -674,8 +731,10 @@ __device__ __forceinline__ void walk_staged(const SingleParams& p, ExpandShared<
             par[i] = sh.x.big.u[r[i]];
         }
         row = next_row;  // the row of the next span's first arc
-        if (kBlocked)
+        if (kMode == kWalkBlocked)
             visit_blocked<kAtomic, kBigUnroll>(p, pos, ok, par, lvl, bits, w0, nw);
+        else if (kMode == kWalkBinned)
+            visit_binned<kAtomic, kBigUnroll>(p, pos, ok, par, lvl, bits, w0);
         else
             visit_arcs<kAtomic, kBigUnroll>(p, pos, ok, par, lvl, lds);
     }
@@ -684,9 +743,10 @@ __device__ __forceinline__ void walk_staged(const SingleParams& p, ExpandShared<
 // Rows above T2: this workgroup's share [a0, a1) of the level's concatenated
 // big-row arcs. Row metadata is staged BLOCK rows at a time (every thread
 // loads one row); the wavefronts then walk the staged arcs.
-template <typename OffT, bool kAtomic, int BLOCK>
+template <typename OffT, bool kAtomic, int BLOCK, int kMode = kWalkProbe>
 __device__ __forceinline__ void expand_big(const SingleParams& p, ExpandShared<BLOCK>& sh, int64_t a0, int64_t a1,
-                                           int lvl, unsigned long long& arcs, const LdsVis& lds) {
+                                           int lvl, unsigned long long& arcs, const LdsVis& lds,
+                                           uint32_t* bin_counts = nullptr) {
     const int tid = threadIdx.x;
     const uint32_t total_rows = big_prefix<BLOCK>(p, sh);
     if (tid == 0) sh.row0 = big_row_at<BLOCK>(p, sh, a0);
@@ -712,12 +772,28 @@ __device__ __forceinline__ void expand_big(const SingleParams& p, ExpandShared<B
         if (tid == nt - 1) sh.staged_end = end;
         __syncthreads();
         const int64_t hi_arc = sh.staged_end;
-        walk_staged<kAtomic, BLOCK, false>(p, sh, from, hi_arc, nt, lvl, lds, nullptr, 0u, 0u);
+        walk_staged<kAtomic, BLOCK, kMode>(p, sh, from, hi_arc, nt, lvl, lds, bin_counts, (uint32_t)blockIdx.x, 0u);
         if (tid == 0) arcs += (unsigned long long)(hi_arc - from);
         from = hi_arc;
         d0 += (uint32_t)nt;
         __syncthreads();
     }
+}
+
+// Rows above T2 at a hub level, into the destination bins: every workgroup
+// (with a share or not) zeroes its LDS counters (one per bin), walks its share,
+// and writes how many entries each of its regions received, so the
+// restoration pass can read every region of a bin.
+template <typename OffT, bool kAtomic, int BLOCK>
+__device__ __forceinline__ void expand_big_binned(const SingleParams& p, ExpandShared<BLOCK>& sh, int64_t a0,
+                                                  int64_t a1, int lvl, unsigned long long& arcs, uint32_t* counts) {
+    const int tid = threadIdx.x;
+    for (int b = tid; b < p.bin_nb; b += BLOCK) counts[b] = 0u;
+    __syncthreads();
+    if (a0 < a1) expand_big<OffT, kAtomic, BLOCK, kWalkBinned>(p, sh, a0, a1, lvl, arcs, LdsVis::none(counts), counts);
+    __syncthreads();
+    uint32_t* mine = p.bin_cnt + (int64_t)blockIdx.x * p.bin_nb;
+    for (int b = tid; b < p.bin_nb; b += BLOCK) mine[b] = min(counts[b], (uint32_t)p.bin_k);
 }
 
 // Rows above T2 on the degree-ordered copy, whose arcs are grouped by
@@ -800,8 +876,8 @@ __device__ __forceinline__ void expand_blocked(const SingleParams& p, ExpandShar
                 sh.x.big.u[tid] = uo;
             }
             __syncthreads();
-            walk_staged<kAtomic, BLOCK, true>(p, sh, 0, tot, nt, lvl, LdsVis::none(bits), bits, (uint32_t)w0,
-                                              (uint32_t)nw);
+            walk_staged<kAtomic, BLOCK, kWalkBlocked>(p, sh, 0, tot, nt, lvl, LdsVis::none(bits), bits,
+                                                      (uint32_t)w0, (uint32_t)nw);
             if (tid == 0) arcs += (unsigned long long)tot;
             from = sh.staged_end;
             d0 += (uint32_t)nt;
@@ -1094,6 +1170,8 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl_arg) {
     }
     unsigned long long arcs = 0;
     const int64_t ta = (int64_t)sh.big_total;
+    // No bins for this level unless its top-down path below decides otherwise.
+    if (p.bin_k > 0 && bid == 0 && tid == 0) st(&p.ctrl->binned[lvl & 1], 0);
 
     // ---- direction (hybrid runs): every workgroup decides the same from the
     // same counters. Bottom-up once the frontier's arcs exceed 1/14 of the arcs
@@ -1148,6 +1226,10 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl_arg) {
 
     extern __shared__ uint32_t hot_lds[];
     const bool large = (int64_t)sh.found >= p.hot_min_frontier;
+    // A hub level: few frontier vertices whose rows above T2 carry many arcs,
+    // nearly all into unvisited heads. Its big-row heads go to destination bins.
+    const bool binned = p.bin_k > 0 && !large && ta >= (int64_t)256 * G;
+    if (binned && bid == 0 && tid == 0) st(&p.ctrl->binned[lvl & 1], 1);
 
     // ---- rows of degree > T2 grouped by destination block (degree-ordered
     // copy, large levels): block by block, the block's visited bits in LDS
@@ -1181,7 +1263,12 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl_arg) {
         if (per < p.min_share) per = p.min_share;
         const int64_t a0 = bid * per;
         const int64_t a1 = a0 + per < ta ? a0 + per : ta;
-        if (a0 < a1) expand_big<OffT, kAtomic, BLOCK>(p, sh, a0, a1, lvl + 1, arcs, lds);
+        if (binned) {
+            expand_big_binned<OffT, kAtomic, BLOCK>(p, sh, a0, a1, lvl + 1, arcs, hot_lds);
+            __syncthreads();  // the word runs below reuse the shared staging
+        } else if (a0 < a1) {
+            expand_big<OffT, kAtomic, BLOCK>(p, sh, a0, a1, lvl + 1, arcs, lds);
+        }
     }
 
     // ---- every other frontier vertex: a contiguous run of words per wavefront
@@ -1238,12 +1325,17 @@ __global__ __launch_bounds__(kRestoreBlock) void k_restore(SingleParams p, int l
     __shared__ unsigned long long red[BLOCK / 64];
     __shared__ uint32_t tmp[BLOCK / 64];
     __shared__ uint32_t listed;  // next-frontier ids of this block so far
+    // Hub levels: the chunk's known visited bits, the bits its bins claim, and
+    // the prefix of its bin regions' counts.
+    __shared__ uint32_t known[BLOCK], claimed[BLOCK];
+    __shared__ uint32_t rpre[kMaxBinGroups + 1];
     // Whether the run has ended and (hybrid runs) the direction of the level
     // just expanded, read in one round where the level is known.
-    int lvl = lvl_arg, dir_bu = 0;
+    int lvl = lvl_arg, dir_bu = 0, binned = 0;
     const int dn = ld(&p.ctrl->done);
     if (lvl_arg >= 0) {
         if (!kAtomic && p.hybrid) dir_bu = ld(&p.ctrl->dir[(lvl + 1) & 1]);
+        if (p.bin_k > 0) binned = ld(&p.ctrl->binned[lvl & 1]);
     } else if (!dn) {
         lvl = ld(&p.ctrl->level);
         if (!kAtomic && p.hybrid) dir_bu = ld(&p.ctrl->dir[(lvl + 1) & 1]);
@@ -1263,15 +1355,87 @@ __global__ __launch_bounds__(kRestoreBlock) void k_restore(SingleParams p, int l
     for (int64_t c = bid; c * BLOCK < p.words; c += G) {
         const int64_t w = c * BLOCK + tid;
         const int lane = tid & 63;
+        // ---- hub level: claim the heads binned for this chunk (bin c). This
+        // block owns the chunk's words until it writes them below, so an LDS
+        // bitmap claims every head exactly once; heads already visited before
+        // the level (the snapshot) or claimed by the expansion's own path (the
+        // current word) are skipped. Claims are recorded with device-scope
+        // stores: the rebuild below reads the level array that way.
+        uint32_t nb_w = 0;
+        if (binned) {
+            if (w < p.words) {
+                known[tid] = ld(p.vis + w) | ld(p.vis_prev + w);
+            } else {
+                known[tid] = ~0u;
+            }
+            claimed[tid] = 0u;
+            const int R = p.bin_groups;
+            constexpr int PER = (kMaxBinGroups + BLOCK - 1) / BLOCK;
+            uint32_t rc[PER], mine = 0;
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int r = tid * PER + k;
+                rc[k] = r < R ? ld(p.bin_cnt + (int64_t)r * p.bin_nb + c) : 0u;
+                mine += rc[k];
+            }
+            uint32_t ex;
+            const uint32_t total = block_excl_scan<BLOCK>(mine, ex, tmp);
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int r = tid * PER + k;
+                if (r < R) rpre[r] = ex;
+                ex += rc[k];
+            }
+            if (tid == 0) rpre[R] = total;
+            __syncthreads();
+            const unsigned long long* bins = reinterpret_cast<const unsigned long long*>(p.bin_e);
+            constexpr int kBinUnroll = 4;
+            for (uint32_t j0 = tid; j0 < total; j0 += BLOCK * kBinUnroll) {
+                unsigned long long e[kBinUnroll];
+                bool ok[kBinUnroll];
+#pragma unroll
+                for (int k = 0; k < kBinUnroll; ++k) {
+                    const uint32_t j = j0 + k * BLOCK;
+                    ok[k] = j < total;
+                    int lo = 0, hi = R - 1;  // the region holding entry j: last with rpre <= j
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (rpre[mid] <= j) lo = mid; else hi = mid - 1;
+                    }
+                    const int64_t at = ((int64_t)c * R + lo) * p.bin_k + (j - rpre[lo]);
+                    e[k] = ok[k] ? ld(bins + at) : 0ull;
+                }
+#pragma unroll
+                for (int k = 0; k < kBinUnroll; ++k) {
+                    if (!ok[k]) continue;
+                    const int32_t v = (int32_t)(uint32_t)e[k];
+                    const int32_t par = (int32_t)(uint32_t)(e[k] >> 32);
+                    const uint32_t wl = ((uint32_t)v >> 5) - (uint32_t)(c * BLOCK);
+                    const uint32_t b = 1u << (v & 31);
+                    if (wl < (uint32_t)BLOCK && !(known[wl] & b) && !(atomicOr(&claimed[wl], b) & b))
+                        record_st(p, v, next, par);
+                }
+            }
+            __threadfence();
+            __syncthreads();
+            nb_w = claimed[tid];
+        }
         uint32_t cur = 0, prev = 0, exact = 0, bm = 0;
         if (w < p.words) {
             cur = ld(p.vis + w);
             prev = ld(p.vis_prev + w);
             bm = p.bigmap[w];  // read-only graph data, read in the same round
         }
-        const bool touched = w < p.words && cur != prev;
+        // Words the expansion's own claims changed (racy in update mode 1),
+        // and words with bin claims only (exact as they are).
+        const bool racy = w < p.words && cur != prev;
+        const bool touched = racy || nb_w != 0u;
+        const uint32_t cur_mem = cur;  // the word as it stands in memory
+        cur |= nb_w;
         if (exact_words) {
             exact = touched ? (cur & ~prev) : 0u;
+        } else if (!__ballot(racy)) {
+            exact = nb_w;
         } else {
             // A racing read-modify-write may have dropped bits (of this level,
             // or of earlier ones through a stale filter read; the snapshot
@@ -1281,7 +1445,8 @@ __global__ __launch_bounds__(kRestoreBlock) void k_restore(SingleParams p, int l
             // one word's 32 levels.
             // Up to kRebuildPairs pairs of touched words per round, all their
             // level reads in flight together.
-            uint64_t tm = __ballot(touched);
+            exact = nb_w;  // words with bin claims only; the racy ones are rebuilt below
+            uint64_t tm = __ballot(racy);
             const int64_t wave_w0 = c * BLOCK + (tid & ~63);
             while (tm) {
                 int wa[kRebuildPairs], wb[kRebuildPairs], lvv[kRebuildPairs];
@@ -1310,7 +1475,7 @@ __global__ __launch_bounds__(kRestoreBlock) void k_restore(SingleParams p, int l
         }
         if (touched) {
             const uint32_t nv = prev | exact;
-            if (cur != nv) st(p.vis + w, nv);
+            if (cur_mem != nv) st(p.vis + w, nv);
             st(p.vis_prev + w, nv);
         }
         // Hot vertices of word w found this level: per hot bit position k,
@@ -1795,9 +1960,19 @@ Grids grids_for(bfs_graph* g, const bfs_tunables& t, int64_t nslots, int lds_wor
 template <typename OffT, int BLOCK, bool kAtomic>
 void launch_typed(bfs_graph* g, const bfs_tunables& t, Workspace* w, SingleParams& p, hipStream_t s,
                   hipEvent_t stop) {
-    const int lds_words = std::max<int>(std::max<int>(p.hot_words, p.full_words),
-                                        p.bseg ? 1 << (p.blk_shift - 5) : 0);
+    const int lds_words = std::max<int>(std::max<int>(std::max<int>(p.hot_words, p.full_words),
+                                                      p.bseg ? 1 << (p.blk_shift - 5) : 0),
+                                        p.bin_e ? p.bin_nb : 0);
     const Grids gr = grids_for<OffT, BLOCK, kAtomic>(g, t, w->nslots, lds_words);
+    // Bins: one region per (bin, expansion workgroup), as many entries as the
+    // workspace's bin storage gives each; too few and the bins stay off.
+    if (p.bin_e && gr.expand <= kMaxBinGroups) {
+        const int64_t k = w->bin_cap / ((int64_t)p.bin_nb * gr.expand);
+        if (k >= 8) {
+            p.bin_k = (int32_t)std::min<int64_t>(k, 1 << 20);
+            p.bin_groups = gr.expand;
+        }
+    }
     // Block-by-block expansion pays off once every workgroup has a few
     // hundred arcs of the big rows to walk.
     p.blk_min_arcs = (int64_t)gr.expand * 256;
@@ -1910,6 +2085,15 @@ void launch_single(bfs_graph* g, const bfs_tunables& t, Workspace* w, int32_t ro
     p.nblk = blocked ? h->nblk : 0;
     p.blk_shift = blocked ? h->blk_shift : 0;
     p.blk_min_arcs = 0;  // set with the grid
+    // Destination bins of hub levels (entries per region set with the grid).
+    const int64_t nbins = (w->words + kRestoreBlock - 1) / kRestoreBlock;
+    const bool bins = t.hub_bins > 0 && w->bin_e && w->bin_cnt && t.sparse_frontier <= 0 &&
+                      nbins <= lds_visited_words_max(t.block_size) && nbins * kMaxBinGroups <= w->bin_cnt_cap;
+    p.bin_e = bins ? w->bin_e : nullptr;
+    p.bin_cnt = bins ? w->bin_cnt : nullptr;
+    p.bin_nb = bins ? (int32_t)nbins : 0;
+    p.bin_k = 0;
+    p.bin_groups = 0;
     p.hot_words = h ? h->hot / 32 : 0;
     p.hot_shift = h ? h->shift : 5;
     p.hot_span = h ? h->span : 0;

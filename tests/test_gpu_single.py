@@ -145,6 +145,32 @@ def test_destination_blocks(scale, blk, flags):
     bfs.bfs_graph_free(dg)
 
 
+@pytest.mark.parametrize("scale,tun,flags", [
+    (16, dict(), 0),                                      # caller's order, separate level and parent arrays
+    (17, dict(update_mode=2), 0),                         # atomicOr claims beside the bins
+    (17, dict(hot_vertices=2048, block_size=1024), 0),    # degree-ordered copy: one record per vertex
+    (17, dict(hot_vertices=2048, block_size=1024), bfs.BFS_HYBRID),
+    (18, dict(blocks_per_cu=2, block_size=256), 0),       # more expansion workgroups, smaller bin regions
+    (16, dict(small_max_degree=8, wave_max_degree=16), 0),  # many rows above T2
+])
+def test_hub_level_bins(scale, tun, flags):
+    """Hub levels (small frontier, many arcs of rows above T2) put their heads in
+    destination bins that the restoration pass claims exactly in LDS: levels
+    exact, parents valid, statistics equal to the oracle's, against the same
+    graph with the bins off."""
+    g = graphgen.rmat(scale, 16, seed=81)
+    dg = load(g, symmetric=True)
+    roots = [int(r) for r in graphgen.pick_roots(g, 4, seed=82)]
+    deg = np.diff(g.offsets)
+    roots.append(int(np.argmax(deg)))  # the largest hub as the root: binned at level 1
+    for bins in (1, -1):
+        bfs.bfs_graph_set_tunables(dg, hub_bins=bins, **tun)
+        assert bfs.bfs_graph_get_tunables(dg)["hub_bins"] == bins
+        for r in roots:
+            check_root(g, dg, r, flags=flags)
+    bfs.bfs_graph_free(dg)
+
+
 def test_erdos_renyi():
     g = graphgen.er(1 << 16, 8, seed=9)
     dg = load(g)

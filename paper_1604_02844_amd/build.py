@@ -34,7 +34,8 @@ def _needs(obj: str, deps: list[str]) -> bool:
 
 def build(force: bool = False, verbose: bool = False) -> str:
     os.makedirs(OUT_DIR, exist_ok=True)
-    headers = [os.path.join(CSRC, "bfs_internal.h"), os.path.join(INCLUDE, "bfs.h")]
+    headers = [os.path.join(CSRC, "bfs_internal.h"), os.path.join(CSRC, "serve_core.h"),
+               os.path.join(INCLUDE, "bfs.h")]
     jobs = []
     objs = []
     for src in SOURCES:

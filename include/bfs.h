@@ -124,10 +124,10 @@ typedef struct {
                                    workgroups) */
     int32_t sparse_frontier;    /* single-root runs: a level whose frontier has at most this
                                    many vertices (at most 4096) and at most 4 times as many arcs
-                                   is expanded by one workgroup from a list of the frontier, with
-                                   exact atomicOr claims, and consecutive such levels run in one
-                                   launch; costs one more launch per level; -1 = off, 0 = library
-                                   default (off) */
+                                   is expanded by the expansion kernel's first workgroup alone,
+                                   from the list of the frontier the previous restoration made,
+                                   with exact atomicOr claims; consecutive such levels run in
+                                   that one launch. -1 = off, 0 = library default (1024) */
     int32_t block_vertices;     /* single-root runs on the degree-ordered copy: rows above T2
                                    keep their arcs grouped by destination block of this many
                                    vertices (a power of two from 2^11 to 2^20, rounded down), and
@@ -150,7 +150,8 @@ typedef struct {
                                    bitmap; the restoration pass, which owns each chunk's visited
                                    words, then claims the binned heads exactly in LDS. 1 = on,
                                    -1 = off, 0 = library default (off: slower at R-MAT scale 24,
-                                   where the scattered entry stores do not combine in L2) */
+                                   where the scattered entry stores do not combine in L2). Bins
+                                   are used only with sparse_frontier off (-1). */
 } bfs_tunables;
 
 /* ---- graph residency ------------------------------------------------------ */

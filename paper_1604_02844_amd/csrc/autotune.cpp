@@ -135,7 +135,8 @@ void autotune(bfs_graph* g, const int32_t* roots, int32_t num_roots, int32_t mod
                 {&bfs_tunables::wave_max_degree, {64, 128, 256, 512, 1024}},
                 {&bfs_tunables::small_max_degree, {8, 16, 32, 64, 256}},
                 {&bfs_tunables::blocks_per_cu, {0, 2, 4}},
-                {&bfs_tunables::block_vertices, {-1, 1 << 20}}};
+                {&bfs_tunables::block_vertices, {-1, 1 << 20}},
+                {&bfs_tunables::sparse_frontier, {-1, 256, 1024, 4096}}};
         // The whole visited bitmap in LDS, where it fits beside every workgroup size.
         if (padded_words(g->n) <= std::min({lds_visited_words_max(256), lds_visited_words_max(512),
                                             lds_visited_words_max(1024)}))

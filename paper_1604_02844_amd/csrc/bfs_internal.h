@@ -32,7 +32,10 @@ constexpr int kStripeStride = 16;  // u64 per stripe (128 bytes)
 // separate cache lines (device-scope atomics on one address serialise) and
 // double-buffered by level parity.
 struct Ctrl {
-    unsigned long long newcnt[2][kStripes * kStripeStride];  // vertices found per level
+    // Vertices found per level (slot 0 of each 128-byte stripe); with small
+    // levels on, slot 1 sums the arcs of the rows restore blocks listed and
+    // slot 2 the ids they listed (blocks that found too many list none).
+    unsigned long long newcnt[2][kStripes * kStripeStride];
     unsigned long long bigarcs[2][kStripes * kStripeStride]; // arcs of the level's big rows
     unsigned long long reached;    // totals, written by the final stats kernel
     unsigned long long arcs;
@@ -41,18 +44,15 @@ struct Ctrl {
     int done;                      // set by the first level that finds an empty frontier
     int num_levels;
     int status;
-    int steps;                     // single-root: steps (small-level kernel, expand, restore) that ran
+    int steps;                     // single-root: expand/restore steps the run used (set when it ends)
     // Direction-optimising runs, indexed by level parity: the direction chosen
     // for the level (1 = bottom-up) and the vertices visited before its frontier.
     int dir[2];
     unsigned long long visited[2];
-    // Single-root level control: the level the next expand/restore pair works
-    // on, whether the small-level kernel already expanded it (the expand then
-    // skips it), and whether a restore ran since the small-level kernel last looked.
-    int level;
-    int skip_e;
-    int r_ran;
-    int pad2;
+    // Levels a step's expansion ran beyond its own, indexed by step parity:
+    // step s works on level s + shift[s & 1] and its expansion writes
+    // shift[(s + 1) & 1] (so a late workgroup of step s still reads its own).
+    int shift[2];
     // Whether the expansion of a level (indexed by its parity) put the heads of
     // its big-row arcs into destination bins for the restoration pass to claim.
     int binned[2];
@@ -259,7 +259,7 @@ constexpr int kMaxRestoreGrid = 1024;
 // Largest LDS snapshot of hot visited words per expansion workgroup (128 KiB).
 constexpr int kMaxHotWords = 32768;
 constexpr int kSmallSeg = 64;      // listed next-frontier ids per restore block
-constexpr int kSmallMax = 4096;    // largest frontier the single-workgroup level kernel takes
+constexpr int kSmallMax = 4096;    // largest frontier one expansion workgroup takes alone
 int restore_grid_for(int64_t words, int cu_count);
 
 // Workspaces are checked out under g->mu; `t` (nullable) receives the graph's

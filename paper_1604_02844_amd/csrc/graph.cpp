@@ -351,7 +351,7 @@ bfs_tunables default_tunables(const bfs_graph* g) {
     const bool fits = g && !large && g->n >= (int64_t)1 << 16 &&
                       padded_words(g->n) <= lds_visited_words_max(1024);
     t.lds_visited = fits ? 1 : -1;
-    t.sparse_frontier = -1;  // measured slower at R-MAT scale 20 and 24 (see the design notes)
+    t.sparse_frontier = 1024;  // the tail of small levels in one workgroup: R-MAT 20 -1%, 24/26 even
     // Destination-blocked expansion of the rows above T2: measured slower at
     // R-MAT scale 24 (the rows' arcs split into short per-block runs), so off.
     t.block_vertices = -1;

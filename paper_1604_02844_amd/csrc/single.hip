@@ -61,7 +61,6 @@ constexpr int kWalkProbe = 0;    // probe, confirm and claim (visit_arcs)
 constexpr int kWalkBlocked = 1;  // heads in the LDS block slice (visit_blocked)
 constexpr int kWalkBinned = 2;   // to the destination bins (visit_binned)
 constexpr int kBuFirst = 4;       // bottom-up: arcs each lane checks before its wavefront helps
-constexpr int kSmallBlock = 1024;  // threads of the small-level kernel
 constexpr int kRebuildPairs = 8;   // restore: pairs of touched words whose levels are read per round
 // Big-row arcs per expansion workgroup above which a level with a small
 // frontier (a hub level) still takes the LDS copy of the visited bits: the
@@ -136,7 +135,7 @@ struct SingleParams {
     int32_t hybrid;            // levels with large frontiers may run bottom-up (symmetric graphs)
     // Small levels: each restore block lists up to kSmallSeg ids of the next
     // frontier (sl) and counts them (sl_cnt); frontiers of at most s_max
-    // vertices and s_arcs arcs go to the single-workgroup level kernel (s_max 0 = off).
+    // vertices and s_arcs arcs are expanded by workgroup 0 alone (s_max 0 = off).
     int32_t* sl;
     int32_t* sl_cnt;
     int32_t s_max;
@@ -480,6 +479,10 @@ struct ExpandShared {
     unsigned long long seen;  // hybrid runs: vertices visited before this frontier
     int was_bu;               // hybrid runs: the previous level ran bottom-up
     int done;                 // the run had already ended
+    int lvl;                  // the level this step expands
+    int shift;                // levels earlier steps ran beyond their own
+    int small;                // the frontier is small enough for workgroup 0 alone
+    uint32_t s_next;          // small levels: next-frontier entries so far
     int64_t staged_end;  // last arc (exclusive) of the staged big rows
     uint32_t row0;
 };
@@ -1083,7 +1086,11 @@ __global__ __launch_bounds__(BLOCK) void k_init(SingleParams p, int nslots) {
         }
     }
     for (int64_t i = gtid; i < 2 * kStripes; i += gsize) {
-        *stripe(p.ctrl, (int)(i / kStripes), (int)(i % kStripes)) = (i == 0) ? 1ull : 0ull;
+        // The first frontier: the root, listed below with the arcs of its row.
+        unsigned long long* sp = stripe(p.ctrl, (int)(i / kStripes), (int)(i % kStripes));
+        sp[0] = (i == 0) ? 1ull : 0ull;
+        sp[1] = (i == 0) ? (unsigned long long)root_deg : 0ull;
+        sp[2] = (i == 0) ? 1ull : 0ull;
         p.ctrl->bigarcs[i / kStripes][(i % kStripes) * kStripeStride] = (i == 0 && root_big) ? (unsigned long long)root_deg : 0ull;
     }
     if (gtid == 0) {
@@ -1095,12 +1102,11 @@ __global__ __launch_bounds__(BLOCK) void k_init(SingleParams p, int nslots) {
         p.ctrl->dir[1] = 0;
         p.ctrl->visited[0] = 0;
         p.ctrl->visited[1] = 0;
-        p.ctrl->level = 0;
-        p.ctrl->skip_e = 0;
-        p.ctrl->r_ran = 0;
         p.ctrl->steps = 0;
+        p.ctrl->shift[0] = 0;
+        p.ctrl->shift[1] = 0;
     }
-    // The first frontier, listed for the small-level kernel: the root alone.
+    // The first frontier, listed for the small-level path: the root alone.
     for (int64_t i = gtid; i < p.restore_grid; i += gsize) {
         p.sl_cnt[i] = i == 0 ? 1 : 0;
         if (i == 0) p.sl[0] = p.root;
@@ -1122,6 +1128,176 @@ __global__ __launch_bounds__(256) void k_out(const unsigned long long* rec, cons
     }
 }
 
+// Row starts (beg) and exclusive arc prefix (pre) of a small-level list of nf
+// ids (nf <= kSmallMax); returns the list's arcs. A thread owns PER
+// consecutive entries. Its sum is clamped above s_arcs, so the total stays in
+// 32 bits and exceeds s_arcs exactly when the true total does (the prefix is
+// then not used).
+template <typename OffT, int BLOCK>
+__device__ __forceinline__ uint32_t small_prefix(const SingleParams& p, ExpandShared<BLOCK>& sh, const int32_t* list,
+                                                 uint32_t nf, int64_t* beg, uint32_t* pre) {
+    constexpr int PER = kSmallMax / BLOCK;
+    const int tid = threadIdx.x;
+    int64_t d[PER];
+    uint64_t mine = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int i = tid * PER + k;
+        d[k] = 0;
+        if (i < (int)nf) {
+            const int32_t u = list[i];
+            const int64_t b = load_off<OffT>(p.off, u);
+            beg[i] = b;
+            d[k] = load_off<OffT>(p.off, (int64_t)u + 1) - b;
+        }
+        mine += (uint64_t)d[k];
+    }
+    const uint32_t cap = (uint32_t)p.s_arcs + 1u;
+    uint32_t at;
+    const uint32_t total = block_excl_scan<BLOCK>(mine < cap ? (uint32_t)mine : cap, at, sh.tmp);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int i = tid * PER + k;
+        if (i < (int)nf) pre[i] = at;
+        at += (uint32_t)d[k];
+    }
+    __syncthreads();
+    return total;
+}
+
+// Small levels (tunable sparse_frontier, s_max > 0), run by workgroup 0 of an
+// expansion whose frontier the previous restore listed in full (at most s_max
+// vertices with at most s_arcs arcs; a restore block with at most kSmallSeg
+// new vertices lists them and counts them and their rows' arcs). Arcs are spread over the
+// threads, claims are exact (atomicOr on the visited word: no other
+// workgroup runs), and the next frontier is listed in LDS. While it stays
+// small the loop goes on to the next level itself, after taking the frontier
+// into the snapshot (and the hot bits). It stops at:
+//  * an empty next frontier: the run is done;
+//  * a large next frontier: the level it just expanded is left to this
+//    step's restore, exactly as the grid expansion leaves a level (claims
+//    recorded, visited bits set, the snapshot unchanged), and the levels it
+//    ran beyond its own go into the next step's shift.
+// LDS (the expansion's dynamic region): two lists, the row starts and the
+// arc prefix of kSmallMax entries each (20 bytes an entry).
+template <typename OffT, int BLOCK>
+__device__ void small_levels(const SingleParams& p, ExpandShared<BLOCK>& sh, uint32_t* dyn, int lvl, int step) {
+    constexpr int PR = (kMaxRestoreGrid + BLOCK - 1) / BLOCK;  // restore blocks per thread
+    int32_t* list[2] = {reinterpret_cast<int32_t*>(dyn), reinterpret_cast<int32_t*>(dyn) + kSmallMax};
+    int64_t* beg = reinterpret_cast<int64_t*>(dyn + 2 * kSmallMax);
+    uint32_t* pre = dyn + 4 * kSmallMax;
+    const int tid = threadIdx.x;
+    const int shift0 = sh.shift;
+    unsigned long long seen = sh.seen;
+
+    // The frontier from the restore blocks' lists, in block order.
+    const int R = p.restore_grid;
+    int cb[PR];
+    uint32_t mine = 0;
+#pragma unroll
+    for (int k = 0; k < PR; ++k) {
+        const int r = tid * PR + k;
+        const int c = r < R ? ld(p.sl_cnt + r) : 0;
+        cb[k] = c < kSmallSeg ? c : kSmallSeg;  // all of them: every block listed all it found
+        mine += (uint32_t)cb[k];
+    }
+    uint32_t ex;
+    uint32_t nf = block_excl_scan<BLOCK>(mine, ex, sh.tmp);
+#pragma unroll
+    for (int k = 0; k < PR; ++k) {
+        const int r = tid * PR + k;
+        for (int j = 0; j < cb[k]; ++j)
+            if (ex + j < (uint32_t)kSmallMax) list[0][ex + j] = ld(p.sl + (int64_t)r * kSmallSeg + j);
+        ex += (uint32_t)cb[k];
+    }
+    if (nf > (uint32_t)kSmallMax) nf = kSmallMax;  // not reached: nf equals the frontier count, at most s_max
+    __syncthreads();
+
+    unsigned long long arcs_done = 0, reached_done = 0;  // this launch's statistics (thread 0)
+    int cur = 0, k_beyond = 0;
+    // Row starts and the exclusive arc prefix of the current list; the arcs
+    // the loop checks are at most s_arcs (the counts checked before the first
+    // level, this pass before the others).
+    uint32_t arcs = small_prefix<OffT, BLOCK>(p, sh, list[0], nf, beg, pre);
+    while (true) {
+        if (tid == 0) sh.s_next = 0;
+        __syncthreads();
+        // Expand: arc a belongs to the last entry whose prefix is at most a.
+        // The claim is the atomicOr itself (no other workgroup runs).
+        int32_t* nxt = list[cur ^ 1];
+        for (uint32_t a = tid; a < arcs; a += BLOCK) {
+            int lo = 0, hi = (int)nf - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (pre[mid] <= a) lo = mid; else hi = mid - 1;
+            }
+            const int32_t u = list[cur][lo];
+            const int32_t v = p.col[beg[lo] + (a - pre[lo])];
+            const uint32_t bit = 1u << (v & 31);
+            if (!(atomicOr(p.vis + ((uint32_t)v >> 5), bit) & bit)) {
+                record(p, v, lvl + 1, out_id(p, u));
+                const uint32_t k = atomicAdd(&sh.s_next, 1u);
+                if (k < (uint32_t)kSmallMax) nxt[k] = v;
+            }
+        }
+        __syncthreads();
+        const uint32_t nn = sh.s_next;
+        if (tid == 0) arcs_done += arcs;
+        if (p.hybrid && tid == 0) {
+            st(&p.ctrl->dir[(lvl + 1) & 1], 0);
+            st(&p.ctrl->visited[(lvl + 1) & 1], seen + nf);
+        }
+        seen += nf;
+        if (nn == 0) {  // nothing new: level lvl + 1 is empty and the run is done
+            if (tid == 0) {
+                st(p.arcs_slot, ld(p.arcs_slot) + arcs_done);
+                st(p.reached_slot, ld(p.reached_slot) + reached_done);
+                p.ctrl->num_levels = lvl + 1;
+                p.ctrl->steps = step + 1;
+                __hip_atomic_store(&p.ctrl->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            return;
+        }
+        // Is the next frontier small too (vertices, then arcs)? Its row starts
+        // and arc prefix replace the current ones (the expansion is over).
+        bool go_on = nn <= (uint32_t)p.s_max;
+        if (go_on) {
+            arcs = small_prefix<OffT, BLOCK>(p, sh, nxt, nn, beg, pre);
+            go_on = arcs <= (uint32_t)p.s_arcs;
+        }
+        if (!go_on) {
+            // Leave level lvl to this step's restore: the next level's counters
+            // start at zero as an expansion would have set them.
+            if (tid < kStripes) {
+                unsigned long long* sp = stripe(p.ctrl, (lvl + 1) & 1, tid);
+                st(sp, 0ull);
+                st(sp + 1, 0ull);
+                st(sp + 2, 0ull);
+                st(&p.ctrl->bigarcs[(lvl + 1) & 1][tid * kStripeStride], 0ull);
+            }
+            if (tid == 0) {
+                st(p.arcs_slot, ld(p.arcs_slot) + arcs_done);
+                st(p.reached_slot, ld(p.reached_slot) + reached_done);
+                st(&p.ctrl->shift[(step + 1) & 1], shift0 + k_beyond);
+            }
+            return;
+        }
+        // The next frontier stays here: the snapshot and the hot bits take it in.
+        for (uint32_t i = tid; i < nn; i += BLOCK) {
+            const int32_t v = nxt[i];
+            atomicOr(p.vis_prev + ((uint32_t)v >> 5), 1u << (v & 31));
+            uint32_t r;
+            if (p.hot_words > 0 && hot_slot((uint32_t)v, (uint32_t)p.hot_span, (uint32_t)p.hot_shift, r))
+                atomicOr(p.hot_vis + (r >> 5), 1u << (r & 31));
+        }
+        if (tid == 0) reached_done += nn;
+        cur ^= 1;
+        nf = nn;
+        ++lvl;
+        ++k_beyond;
+    }
+}
+
 // Expansion of level `lvl` (frontier bitmap p.fr).
 template <typename OffT, int BLOCK, bool kAtomic>
 __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl_arg) {
@@ -1129,52 +1305,85 @@ __global__ __launch_bounds__(BLOCK) void k_expand(SingleParams p, int lvl_arg) {
     __shared__ ExpandShared<BLOCK> sh;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int64_t G = gridDim.x, bid = blockIdx.x;
-    // With the small-level kernel on (lvl_arg < 0) the level lives in the
-    // control block, and that kernel may have expanded it already.
-    int lvl = lvl_arg;
-    if (lvl_arg < 0) {
-        if (ld(&p.ctrl->done)) return;
-        if (ld(&p.ctrl->skip_e)) return;
-        lvl = ld(&p.ctrl->level);
-    }
-
-    // Whether the run has ended, the frontier size and the arcs of the
-    // frontier's rows above T2 (both counted by the previous restore), and
-    // the direction state: all read in one round (small levels are bound by
-    // such round trips).
+    // Step lvl_arg expands level lvl_arg + shift (small levels on; else shift
+    // is 0). Whether the run has ended, the frontier size and the arcs of the
+    // frontier's rows above T2 (both counted by the previous restore), the
+    // small-level counts and the direction state are all read in one round
+    // (small levels are bound by such round trips): both parities, since the
+    // level's parity is known only with the shift.
     if (tid < 64) {
-        int dn = 0, wb = 0;
-        unsigned long long sn = 0;
+        int dn = 0, a = 0, wb[2] = {0, 0};
+        unsigned long long sn[2] = {0, 0};
         if (tid == 0) {
-            if (lvl_arg >= 0) dn = ld(&p.ctrl->done);
+            dn = ld(&p.ctrl->done);
+            if (p.s_max > 0) a = ld(&p.ctrl->shift[lvl_arg & 1]);
             if (p.hybrid) {
-                wb = ld(&p.ctrl->dir[lvl & 1]);
-                sn = ld(&p.ctrl->visited[lvl & 1]);
+                wb[0] = ld(&p.ctrl->dir[0]);
+                wb[1] = ld(&p.ctrl->dir[1]);
+                sn[0] = ld(&p.ctrl->visited[0]);
+                sn[1] = ld(&p.ctrl->visited[1]);
             }
         }
-        unsigned long long c = ld(stripe(p.ctrl, lvl & 1, tid));
-        unsigned long long b = ld(&p.ctrl->bigarcs[lvl & 1][tid * kStripeStride]);
-        c = wave_sum(c);
-        b = wave_sum(b);
+        const unsigned long long c0 = ld(stripe(p.ctrl, 0, tid)), c1 = ld(stripe(p.ctrl, 1, tid));
+        const unsigned long long b0 = ld(&p.ctrl->bigarcs[0][tid * kStripeStride]);
+        const unsigned long long b1 = ld(&p.ctrl->bigarcs[1][tid * kStripeStride]);
+        unsigned long long sa0 = 0, sa1 = 0, sl0 = 0, sl1 = 0;  // listed arcs and ids
+        if (p.s_max > 0) {
+            sa0 = ld(stripe(p.ctrl, 0, tid) + 1);
+            sa1 = ld(stripe(p.ctrl, 1, tid) + 1);
+            sl0 = ld(stripe(p.ctrl, 0, tid) + 2);
+            sl1 = ld(stripe(p.ctrl, 1, tid) + 2);
+        }
+        a = __shfl(a, 0, 64);
         dn = __shfl(dn, 0, 64);
+        const int lv = lvl_arg + a, q = lv & 1;
+        const unsigned long long c = wave_sum(q ? c1 : c0);
+        const unsigned long long b = wave_sum(q ? b1 : b0);
+        const unsigned long long sa = p.s_max > 0 ? wave_sum(q ? sa1 : sa0) : 0ull;
+        const unsigned long long sl = p.s_max > 0 ? wave_sum(q ? sl1 : sl0) : 0ull;
         if (tid == 0) {
             sh.done = dn;
+            sh.lvl = lv;
+            sh.shift = a;
             sh.found = c;
             sh.big_total = b;
-            sh.was_bu = wb;
-            sh.seen = sn;
+            sh.was_bu = wb[q];
+            sh.seen = sn[q];
+            // Small: every new vertex listed, few enough, with few enough arcs.
+            sh.small = p.s_max > 0 && sl == c && c <= (unsigned long long)p.s_max &&
+                       sa <= (unsigned long long)p.s_arcs;
         }
-        if (bid == 0 && !dn) {  // counters for the next level
-            st(stripe(p.ctrl, (lvl + 1) & 1, tid), 0ull);
-            st(&p.ctrl->bigarcs[(lvl + 1) & 1][tid * kStripeStride], 0ull);
+        if (bid == 0 && !dn) {  // counters for the next level, and the next step's shift
+            unsigned long long* sp = stripe(p.ctrl, (lv + 1) & 1, tid);
+            st(sp, 0ull);
+            st(&p.ctrl->bigarcs[(lv + 1) & 1][tid * kStripeStride], 0ull);
+            if (p.s_max > 0) {
+                st(sp + 1, 0ull);
+                st(sp + 2, 0ull);
+                if (tid == 0) st(&p.ctrl->shift[(lvl_arg + 1) & 1], a);
+            }
         }
     }
     __syncthreads();
     if (sh.done) return;
+    const int lvl = sh.lvl;
     if (sh.found == 0) {
         if (bid == 0 && tid == 0) {
             p.ctrl->num_levels = lvl;
+            p.ctrl->steps = lvl_arg + 1;
             __hip_atomic_store(&p.ctrl->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        return;
+    }
+    // ---- a small frontier (a short list with few arcs): workgroup 0 expands
+    // it, and the small levels after it, alone; the others leave at once. This
+    // comes before the direction choice: the loop rewrites counters that a
+    // workgroup starting late reads, and with them it can only see a smaller
+    // frontier (or none), which brings it here (or to the return above) too.
+    if (sh.small) {
+        if (bid == 0) {
+            extern __shared__ uint32_t small_lds[];
+            small_levels<OffT, BLOCK>(p, sh, small_lds, lvl, lvl_arg);
         }
         return;
     }
@@ -1334,30 +1543,36 @@ template <typename OffT, bool kAtomic>
 __global__ __launch_bounds__(kRestoreBlock) void k_restore(SingleParams p, int lvl_arg) {
     constexpr int BLOCK = kRestoreBlock;
     __shared__ unsigned long long red[BLOCK / 64];
+    __shared__ unsigned long long red_arcs[BLOCK / 64];
     __shared__ uint32_t tmp[BLOCK / 64];
-    __shared__ uint32_t listed;  // next-frontier ids of this block so far
+    __shared__ uint32_t listed;  // next-frontier vertices of this block so far (the first kSmallSeg listed)
+    __shared__ int32_t lids[kSmallSeg];  // the listed ids
     // Hub levels: the chunk's known visited bits, the bits its bins claim, and
     // the prefix of its bin regions' counts.
     __shared__ uint32_t known[BLOCK], claimed[BLOCK];
     __shared__ uint32_t rpre[kMaxBinGroups + 1];
-    // Whether the run has ended and (hybrid runs) the direction of the level
-    // just expanded, read in one round where the level is known.
-    int lvl = lvl_arg, dir_bu = 0, binned = 0;
+    // Whether the run has ended, the level (step lvl_arg restores level
+    // lvl_arg + the shift its expansion wrote) and (hybrid runs) the direction
+    // of the level just expanded, read in one round (both parities).
+    int binned = 0;
     const int dn = ld(&p.ctrl->done);
-    if (lvl_arg >= 0) {
-        if (!kAtomic && p.hybrid) dir_bu = ld(&p.ctrl->dir[(lvl + 1) & 1]);
-        if (p.bin_k > 0) binned = ld(&p.ctrl->binned[lvl & 1]);
-    } else if (!dn) {
-        lvl = ld(&p.ctrl->level);
-        if (!kAtomic && p.hybrid) dir_bu = ld(&p.ctrl->dir[(lvl + 1) & 1]);
+    const int sft = p.s_max > 0 ? ld(&p.ctrl->shift[(lvl_arg + 1) & 1]) : 0;
+    int d2[2] = {0, 0};
+    if (!kAtomic && p.hybrid) {
+        d2[0] = ld(&p.ctrl->dir[0]);
+        d2[1] = ld(&p.ctrl->dir[1]);
     }
+    if (p.bin_k > 0) binned = ld(&p.ctrl->binned[lvl_arg & 1]);  // bins are off with small levels: no shift
     if (dn) return;
+    const int lvl = lvl_arg + sft;
+    const int dir_bu = d2[(lvl + 1) & 1];
     const int tid = threadIdx.x;
     if (tid == 0) listed = 0;
     __syncthreads();
     const int64_t G = gridDim.x, bid = blockIdx.x;
     const int next = lvl + 1;
     unsigned long long found = 0;
+    unsigned long long list_arcs = 0;  // arcs of the rows this thread listed
     uint32_t seg_n = 0, seg_a = 0;  // running totals of this block's segment
     const int32_t first = p.seg_start[bid];
     // A bottom-up level wrote every changed word once, from its owner, with
@@ -1510,12 +1725,19 @@ __global__ __launch_bounds__(kRestoreBlock) void k_restore(SingleParams p, int l
             st(p.fr + w, exact);
             found += (unsigned long long)__popc(exact);
         }
-        // List the block's next-frontier ids while there are few (for the
-        // small-level kernel).
-        if (p.s_max > 0 && exact) {
-            uint32_t at = atomicAdd(&listed, (uint32_t)__popc(exact));
+        // List the block's next-frontier ids in LDS while there are few (for
+        // the small-level path): one LDS atomic per wavefront, positions from
+        // a wave scan.
+        if (p.s_max > 0) {
+            const int cnt = __popc(exact);
+            const int inc = wave_incl_scan(cnt, lane);
+            const int tot = __shfl(inc, 63, 64);
+            uint32_t base = 0;
+            if (lane == 63 && tot > 0) base = atomicAdd(&listed, (uint32_t)tot);
+            base = (uint32_t)__shfl((int)base, 63, 64);
+            uint32_t at = base + (uint32_t)(inc - cnt);
             for (uint32_t x = exact; x && at < (uint32_t)kSmallSeg; x &= x - 1, ++at)
-                st(p.sl + bid * kSmallSeg + at, (int32_t)(w * 32 + __builtin_ctz(x)));
+                lids[at] = (int32_t)(w * 32 + __builtin_ctz(x));
         }
         // Append the next frontier's big rows of this chunk to the segment.
         const uint32_t big = exact & bm;
@@ -1544,6 +1766,20 @@ __global__ __launch_bounds__(kRestoreBlock) void k_restore(SingleParams p, int l
     found = wave_sum(found);
     if ((tid & 63) == 0) red[tid >> 6] = found;
     __syncthreads();
+    // A block that listed its whole next frontier publishes the ids and the
+    // arcs of their rows; one with more leaves the level to the grid (the
+    // offset reads stay off the large levels, where nearly every block has more).
+    const uint32_t nl = p.s_max > 0 ? listed : 0u;
+    if (p.s_max > 0 && nl <= (uint32_t)kSmallSeg) {
+        if (tid < (int)nl) {
+            const int64_t v = lids[tid];
+            st(p.sl + bid * kSmallSeg + tid, (int32_t)v);
+            list_arcs = (unsigned long long)(load_off<OffT>(p.off, v + 1) - load_off<OffT>(p.off, v));
+        }
+        list_arcs = wave_sum(list_arcs);
+        if ((tid & 63) == 0) red_arcs[tid >> 6] = list_arcs;
+        __syncthreads();
+    }
     if (tid == 0) {
         unsigned long long a = 0;
         for (int i = 0; i < BLOCK / 64; ++i) a += red[i];
@@ -1555,185 +1791,17 @@ __global__ __launch_bounds__(kRestoreBlock) void k_restore(SingleParams p, int l
         st(p.seg_arcs + bid, seg_a);
         if (seg_a) atomicAdd(&p.ctrl->bigarcs[next & 1][(bid % kStripes) * kStripeStride], (unsigned long long)seg_a);
         if (p.s_max > 0) {
-            st(p.sl_cnt + bid, (int32_t)listed);
-            if (bid == 0) st(&p.ctrl->r_ran, 1);
-        }
-    }
-}
-
-// Small levels (a sparse frontier; tunable sparse_frontier, off by default),
-// one workgroup, launched before every expand/restore pair. It first advances the run's level past a restore that
-// ran, then, while the frontier is a short list (at most s_max vertices and
-// s_arcs arcs), expands it itself: arcs are spread over the threads, claims
-// are exact (atomicOr on the visited word), and the next frontier is listed in
-// LDS. Consecutive small levels run in this one launch. It stops at:
-//  * an empty next frontier: the run is done;
-//  * a large next frontier: the level it just expanded is left for the
-//    following restore, exactly as an expansion would leave it (claims
-//    recorded, visited bits set, the snapshot unchanged), and the following
-//    expansion is told to skip it.
-// A frontier that is large from the start is left to the expansion kernel.
-template <typename OffT>
-__global__ __launch_bounds__(kSmallBlock) void k_small(SingleParams p) {
-    constexpr int B = kSmallBlock;
-    constexpr int PER = kSmallMax / B;  // list entries per thread
-    __shared__ int32_t list[2][kSmallMax];
-    __shared__ int64_t beg[kSmallMax];
-    __shared__ uint32_t pre[kSmallMax];  // exclusive arc prefix of the current list
-    __shared__ uint32_t tmp[B / 64];
-    __shared__ unsigned long long red[B / 64];
-    __shared__ int s_lvl, s_over;
-    __shared__ uint32_t s_next;
-    const int tid = threadIdx.x, lane = tid & 63;
-    if (ld(&p.ctrl->done)) return;
-    if (tid == 0) {
-        int lvl = ld(&p.ctrl->level);
-        if (ld(&p.ctrl->r_ran)) {
-            ++lvl;
-            st(&p.ctrl->level, lvl);
-            st(&p.ctrl->r_ran, 0);
-        }
-        st(&p.ctrl->skip_e, 0);
-        st(&p.ctrl->steps, ld(&p.ctrl->steps) + 1);
-        s_lvl = lvl;
-        s_over = 0;
-        s_next = 0;
-    }
-    __syncthreads();
-    if (p.s_max <= 0) return;
-    int lvl = s_lvl;
-
-    // The frontier from the restore blocks' lists (one block per thread).
-    const int R = p.restore_grid;
-    const int cb = tid < R ? ld(p.sl_cnt + tid) : 0;
-    if (cb > kSmallSeg) s_over = 1;
-    uint32_t excl;
-    uint32_t nf = block_excl_scan<B>((uint32_t)(cb > kSmallSeg ? 0 : cb), excl, tmp);
-    if (s_over || nf == 0 || nf > (uint32_t)p.s_max) return;  // the expansion kernel takes it
-    for (int k = 0; k < cb; ++k) list[0][excl + k] = ld(p.sl + tid * kSmallSeg + k);
-    __syncthreads();
-
-    unsigned long long arcs_done = 0, reached_done = 0;  // this launch's statistics (thread 0)
-    unsigned long long seen = p.hybrid ? ld(&p.ctrl->visited[lvl & 1]) : 0;
-    int cur = 0;
-    bool first = true;
-    while (true) {
-        // Row starts and the exclusive arc prefix of the current list.
-        int64_t d[PER];
-        unsigned long long mine = 0;
-#pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            const int i = tid * PER + k;
-            d[k] = 0;
-            if (i < (int)nf) {
-                const int32_t u = list[cur][i];
-                const int64_t b = load_off<OffT>(p.off, u);
-                beg[i] = b;
-                d[k] = load_off<OffT>(p.off, (int64_t)u + 1) - b;
-            }
-            mine += (unsigned long long)d[k];
-        }
-        if (first) {
-            // Checked in 64 bits: a few hub rows can exceed any 32-bit prefix.
-            unsigned long long tot = wave_sum(mine);
-            if (lane == 0) red[tid >> 6] = tot;
-            __syncthreads();
-            tot = 0;
-            for (int i = 0; i < B / 64; ++i) tot += red[i];
-            __syncthreads();
-            if ((int64_t)tot > p.s_arcs) return;  // too many arcs: the expansion kernel takes it
-            first = false;
-        }
-        // From here the level has at most s_arcs arcs: 32-bit prefixes suffice.
-        uint32_t at;
-        const uint32_t arcs = block_excl_scan<B>((uint32_t)mine, at, tmp);
-#pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            const int i = tid * PER + k;
-            if (i < (int)nf) pre[i] = at;
-            at += (uint32_t)d[k];
-        }
-        __syncthreads();
-        // Expand: arc a belongs to the last entry whose prefix is at most a.
-        int32_t* nxt = list[cur ^ 1];
-        for (uint32_t a = tid; a < arcs; a += B) {
-            int lo = 0, hi = (int)nf - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (pre[mid] <= a) lo = mid; else hi = mid - 1;
-            }
-            const int32_t u = list[cur][lo];
-            const int32_t v = p.col[beg[lo] + (a - pre[lo])];
-            const uint32_t bit = 1u << (v & 31);
-            uint32_t* wp = p.vis + ((uint32_t)v >> 5);
-            if (!(ld(wp) & bit) && !(atomicOr(wp, bit) & bit)) {
-                record(p, v, lvl + 1, out_id(p, u));
-                const uint32_t k = atomicAdd(&s_next, 1u);
-                if (k < (uint32_t)kSmallMax) nxt[k] = v;
+            st(p.sl_cnt + bid, (int32_t)nl);
+            // Only blocks that listed all their ids count them (so the sum
+            // equals the level's count exactly when every block did).
+            if (nl > 0 && nl <= (uint32_t)kSmallSeg) {
+                unsigned long long sa = 0;
+                for (int i = 0; i < BLOCK / 64; ++i) sa += red_arcs[i];
+                unsigned long long* sp = stripe(p.ctrl, next & 1, (int)(bid % kStripes));
+                atomicAdd(sp + 1, sa);
+                atomicAdd(sp + 2, (unsigned long long)nl);
             }
         }
-        __syncthreads();
-        const uint32_t nn = s_next;
-        if (tid == 0) arcs_done += arcs;
-        if (p.hybrid && tid == 0) {
-            st(&p.ctrl->dir[(lvl + 1) & 1], 0);
-            st(&p.ctrl->visited[(lvl + 1) & 1], seen + nf);
-        }
-        seen += nf;
-        if (nn == 0) {  // nothing new: level lvl + 1 is empty and the run is done
-            if (tid == 0) {
-                st(p.arcs_slot, ld(p.arcs_slot) + arcs_done);
-                st(p.reached_slot, ld(p.reached_slot) + reached_done);
-                p.ctrl->num_levels = lvl + 1;
-                __hip_atomic_store(&p.ctrl->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            return;
-        }
-        // Is the next frontier small too (vertices, then arcs)?
-        unsigned long long next_arcs = 0;
-        if (nn <= (uint32_t)p.s_max) {
-            for (uint32_t i = tid; i < nn; i += B) {
-                const int32_t v = nxt[i];
-                next_arcs += (unsigned long long)(load_off<OffT>(p.off, (int64_t)v + 1) - load_off<OffT>(p.off, v));
-            }
-            next_arcs = wave_sum(next_arcs);
-            if (lane == 0) red[tid >> 6] = next_arcs;
-            __syncthreads();
-            next_arcs = 0;
-            for (int i = 0; i < B / 64; ++i) next_arcs += red[i];
-        }
-        const bool go_on = nn <= (uint32_t)p.s_max && (int64_t)next_arcs <= p.s_arcs;
-        if (!go_on) {
-            // Leave level lvl to the following restore: its counters start at
-            // zero as an expansion would have set them, and that expansion skips.
-            if (tid < kStripes) {
-                st(stripe(p.ctrl, (lvl + 1) & 1, tid), 0ull);
-                st(&p.ctrl->bigarcs[(lvl + 1) & 1][tid * kStripeStride], 0ull);
-            }
-            if (tid == 0) {
-                st(p.arcs_slot, ld(p.arcs_slot) + arcs_done);
-                st(p.reached_slot, ld(p.reached_slot) + reached_done);
-                st(&p.ctrl->level, lvl);
-                st(&p.ctrl->skip_e, 1);
-            }
-            return;
-        }
-        // The next frontier stays here: the snapshot and the hot bits take it in.
-        for (uint32_t i = tid; i < nn; i += B) {
-            const int32_t v = nxt[i];
-            atomicOr(p.vis_prev + ((uint32_t)v >> 5), 1u << (v & 31));
-            uint32_t r;
-            if (p.hot_words > 0 && hot_slot((uint32_t)v, (uint32_t)p.hot_span, (uint32_t)p.hot_shift, r))
-                atomicOr(p.hot_vis + (r >> 5), 1u << (r & 31));
-        }
-        if (tid == 0) {
-            reached_done += nn;
-            s_next = 0;
-        }
-        __syncthreads();
-        cur ^= 1;
-        nf = nn;
-        ++lvl;
     }
 }
 
@@ -1971,9 +2039,12 @@ Grids grids_for(bfs_graph* g, const bfs_tunables& t, int64_t nslots, int lds_wor
 template <typename OffT, int BLOCK, bool kAtomic>
 void launch_typed(bfs_graph* g, const bfs_tunables& t, Workspace* w, SingleParams& p, hipStream_t s,
                   hipEvent_t stop) {
-    const int lds_words = std::max<int>(std::max<int>(std::max<int>(p.hot_words, p.full_words),
-                                                      p.bseg ? 1 << (p.blk_shift - 5) : 0),
-                                        p.bin_e ? p.bin_nb : 0);
+    // Dynamic LDS: the largest of the visited copy, a destination block, the
+    // bin counters and the small-level lists (5 words an entry).
+    const int lds_words = std::max<int>(std::max<int>(std::max<int>(std::max<int>(p.hot_words, p.full_words),
+                                                                    p.bseg ? 1 << (p.blk_shift - 5) : 0),
+                                                      p.bin_e ? p.bin_nb : 0),
+                                        p.s_max > 0 ? 5 * kSmallMax : 0);
     const Grids gr = grids_for<OffT, BLOCK, kAtomic>(g, t, w->nslots, lds_words);
     // Bins: one region per (bin, expansion workgroup), as many entries as the
     // workspace's bin storage gives each; too few and the bins stay off.
@@ -1991,17 +2062,15 @@ void launch_typed(bfs_graph* g, const bfs_tunables& t, Workspace* w, SingleParam
     k_init<OffT, BLOCK><<<init_grid, BLOCK, 0, s>>>(p, (int)w->nslots);
     BFS_HIP(hipGetLastError());
     // Steps are enqueued in chunks; between chunks the host reads the done
-    // flag. A step is the small-level kernel (which advances the level and runs
-    // any small levels), then one expansion and one restoration; the level
-    // each works on lives in the control block. The first chunk covers as many
-    // steps as the previous run on this workspace used (runs from other roots
-    // of one graph have similar shapes), so most runs end inside it.
-    // Without the small-level kernel a step is one level, passed as an argument.
+    // flag. A step is one expansion and one restoration; step s works on level
+    // s plus the levels earlier small-level loops ran beyond their own (kept
+    // in the control block). The first chunk covers as many steps as the
+    // previous run on this workspace used (runs from other roots of one graph
+    // have similar shapes), so most runs end inside it.
     // When the previous run's step count says this chunk ends the run, the
     // output pass and the stop event go in before the host waits, so the
     // host's wake-up is not inside the timed span; if the run goes on, a later
     // chunk repeats both.
-    const bool small = p.s_max > 0;
     const int64_t expect = w->last_launches;  // 0: unknown
     int64_t steps = 0;
     int chunk = std::max(4, std::min(64, w->last_launches + 1));
@@ -2017,10 +2086,9 @@ void launch_typed(bfs_graph* g, const bfs_tunables& t, Workspace* w, SingleParam
     };
     while (true) {
         for (int i = 0; i < chunk; ++i) {
-            const int lvl = small ? -1 : (int)(steps + i);
-            if (small) k_small<OffT><<<1, kSmallBlock, 0, s>>>(p);
-            k_expand<OffT, BLOCK, kAtomic><<<gr.expand, BLOCK, (size_t)lds_words * 4, s>>>(p, lvl);
-            k_restore<OffT, kAtomic><<<gr.restore, kRestoreBlock, 0, s>>>(p, lvl);
+            const int step = (int)(steps + i);
+            k_expand<OffT, BLOCK, kAtomic><<<gr.expand, BLOCK, (size_t)lds_words * 4, s>>>(p, step);
+            k_restore<OffT, kAtomic><<<gr.restore, kRestoreBlock, 0, s>>>(p, step);
         }
         BFS_HIP(hipGetLastError());
         steps += chunk;
@@ -2033,7 +2101,7 @@ void launch_typed(bfs_graph* g, const bfs_tunables& t, Workspace* w, SingleParam
         chunk = chunk < 64 ? chunk * 2 : 64;
     }
     // The step that found the frontier empty was the last one with work.
-    if (w->host_ctrl->done) w->last_launches = small ? w->host_ctrl->steps : w->host_ctrl->num_levels + 1;
+    if (w->host_ctrl->done) w->last_launches = w->host_ctrl->steps;
     if (!finished_early) finish();
 }
 
@@ -2126,7 +2194,7 @@ void launch_single(bfs_graph* g, const bfs_tunables& t, Workspace* w, int32_t ro
     p.sl_cnt = w->sl_cnt;
     p.s_max = t.sparse_frontier > 0 ? std::min(t.sparse_frontier, kSmallMax) : 0;
     p.s_arcs = (int64_t)p.s_max * 4;
-    if (!p.sl || !p.sl_cnt || g->restore_grid > kSmallBlock) fail(BFS_E_INTERNAL, "small-level lists out of range");
+    if (!p.sl || !p.sl_cnt || g->restore_grid > kMaxRestoreGrid) fail(BFS_E_INTERNAL, "small-level lists out of range");
     const bool off32 = !h && g->off32;
     const bool atomic = t.update_mode == 2;
 #define BFS_LAUNCH(OFFT, BS)                                         \

@@ -164,7 +164,8 @@ def test_hub_level_bins(scale, tun, flags):
     deg = np.diff(g.offsets)
     roots.append(int(np.argmax(deg)))  # the largest hub as the root: binned at level 1
     for bins in (1, -1):
-        bfs.bfs_graph_set_tunables(dg, hub_bins=bins, **tun)
+        # Bins are used only with the small-level path off.
+        bfs.bfs_graph_set_tunables(dg, hub_bins=bins, sparse_frontier=-1, **tun)
         assert bfs.bfs_graph_get_tunables(dg)["hub_bins"] == bins
         for r in roots:
             check_root(g, dg, r, flags=flags)
@@ -286,11 +287,16 @@ def test_lds_visited_defaults_and_limit():
 def test_small_level_kernel_shapes(sparse):
     """Long chains of small levels (paths, a cycle, a binary tree, a star whose
     leaves all land in one restore block's list, a broom: a path into a big
-    star) give the same levels and valid parents with the single-workgroup
-    level kernel off, at its default, and at tight limits."""
+    star, and a path, a star of 3000 leaves, then another path: small levels
+    run in one workgroup twice with grid levels between, so the level offset
+    they leave to later steps grows twice) give the same levels and valid
+    parents with the small-level path off, at its default, and at tight limits."""
+    two_tails = graphgen.from_edges(3201, list(range(50)) + [50] * 3000 + [3050] + list(range(3051, 3200)),
+                                    list(range(1, 51)) + list(range(51, 3051)) + [3051] + list(range(3052, 3201)))
     cases = [(graphgen.path(3000), 0), (graphgen.path(3000), 1500), (graphgen.cycle(2001), 5),
              (graphgen.binary_tree(1 << 13), 0), (graphgen.star(5000), 0), (graphgen.star(5000), 17),
-             (graphgen.from_edges(3000, list(range(999)) + [999] * 2000, list(range(1, 1000)) + list(range(1000, 3000))), 0)]
+             (graphgen.from_edges(3000, list(range(999)) + [999] * 2000, list(range(1, 1000)) + list(range(1000, 3000))), 0),
+             (two_tails, 0)]
     for g, r in cases:
         dg = load(g)
         bfs.bfs_graph_set_tunables(dg, sparse_frontier=sparse)

@@ -39,7 +39,13 @@ typedef unsigned long long u64;
 constexpr int kUnroll = 2;
 constexpr int kPullUnroll = 8;
 constexpr int kPullHead = 32;  // arcs a lane scans on its own before its wavefront helps
-constexpr int kPushAlpha = 12;  // push while (arcs of the frontier rows) * alpha < nnz
+// Push while (arcs of the frontier rows) * alpha < nnz. A pull at an early
+// dense level scans whole rows (few vertices find all their missing roots in
+// one level), so it costs about nnz gathers, and a push arc (probe, atomicOr,
+// record) about 4 gathers. Measured per batch (R-MAT 22 x64, ER 2^22 d16 x64
+// and x8, ms): alpha 12: 10.1, 8.26, 3.49; 6: 10.1, 8.26, 2.97; 4: 7.37, 8.31,
+// 3.01; 3: 7.34, 8.25, 3.28; 2: 7.40, 8.29, 3.33; 1: 21.4, 27.5, 5.86.
+constexpr int kPushAlpha = 4;
 
 struct MsParams {
     const void* off;

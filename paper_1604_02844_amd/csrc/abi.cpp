@@ -237,8 +237,9 @@ int bfs_run_batch(bfs_graph* g, const int32_t* roots, int32_t num_roots, int32_t
                     pa = w->out_parents;
                 }
                 BFS_HIP(hipEventRecord(w->ev_start, s));
-                bfs::ms_run_batch(g, t, w, roots + g0, cnt, lv, pa, g->n, s);
-                BFS_HIP(hipEventRecord(w->ev_stop, s));
+                // The stop event goes in after the batch's last kernel, before
+                // the host's last wait when the batch ends as expected.
+                bfs::ms_run_batch(g, t, w, roots + g0, cnt, lv, pa, g->n, s, w->ev_stop);
                 if (host_out) {
                     BFS_HIP(hipMemcpyAsync(levels + (int64_t)g0 * g->n, lv, (size_t)cnt * g->n * 4,
                                            hipMemcpyDeviceToHost, s));

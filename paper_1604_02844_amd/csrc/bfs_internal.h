@@ -135,6 +135,8 @@ struct MsWorkspace {
     hipEvent_t ev_start = nullptr, ev_stop = nullptr, ev_free = nullptr;
     bool used = false;
     int64_t bytes = 0;
+    int last_levels = 0;  // level steps the previous batch on this workspace enqueued until it ended (0: none yet)
+    double last_unreached = 1.0;  // fraction of (root, vertex) pairs the previous batch left unreached
 };
 
 // Rows with degree above a threshold, for one vertex order: their ids, the
@@ -302,7 +304,7 @@ void launch_fill_i32(int32_t* p, int64_t count, int32_t value, hipStream_t s);
 // Multi-source engine (multi.hip). A batch runs every level device-side with
 // chunked host checks; the server steps one level at a time.
 void ms_run_batch(bfs_graph* g, const bfs_tunables& t, MsWorkspace* w, const int32_t* roots, int32_t count,
-                  int32_t* levels, int32_t* parents, int64_t ld, hipStream_t s);
+                  int32_t* levels, int32_t* parents, int64_t ld, hipStream_t s, hipEvent_t stop = nullptr);
 void ms_reset(bfs_graph* g, MsWorkspace* w, hipStream_t s);
 // Seed slots (host arrays) into the frontier of instance level `level`: root
 // bits and level-0 outputs. The slot output pointers and start levels must

@@ -80,6 +80,31 @@ def test_batch_tunables(tun):
     check_batch(g, dg, graphgen.pick_roots(g, 20, seed=38))
 
 
+def test_unreached_fill_and_final_pass():
+    """Unreached (root, vertex) pairs get -1 from a fill before the batch (the
+    first batch on a workspace, or after one that left many pairs unreached)
+    or from a pass after it that writes only those pairs (after a batch that
+    reached nearly every pair). On one workspace: a batch in a large connected
+    component (fill; 0.6% of pairs unreached), one confined to a 50-vertex path
+    (pass, with nearly every pair unreached), the same again (fill), then the
+    large component twice (fill, then pass). Outputs start as uninitialised
+    memory, so a pair written by neither shows up. Every row exact."""
+    big = graphgen.er(1 << 13, 16, seed=91)
+    g = graphgen.disjoint(big, graphgen.path(50))
+    dg = load(g)
+    roots_big = graphgen.pick_roots(big, 32, seed=92)
+    roots_small = [big.n + 3, big.n + 10, big.n + 49]
+    for roots in (roots_big, roots_small, roots_small, roots_big, roots_big):
+        check_batch(g, dg, roots)
+    # Host outputs (staging rows) after a batch that chose the pass.
+    lv = np.empty((len(roots_big), g.n), dtype=np.int32)
+    pa = np.empty((len(roots_big), g.n), dtype=np.int32)
+    bfs.bfs_run_batch(dg, roots_big, lv, pa)
+    for i, r in enumerate(roots_big):
+        ref, _, _ = oracle.bfs(g.offsets, g.cols, int(r))
+        assert oracle.validate(g.offsets, g.cols, int(r), ref, lv[i], pa[i])[0] == 0
+
+
 def test_batch_int32_offsets_and_host_output():
     g = graphgen.rmat(10, 16, seed=1)
     dg = load(g, offsets_i32=True)

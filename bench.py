@@ -145,6 +145,9 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="also run a plain copy kernel of BYTES (read and written) for counter scaling")
     ap.add_argument("--mode", default="single", choices=["single", "batch", "serve", "ceilings"])
+    ap.add_argument("--batch-case", default="", metavar="GRAPH:ROOTS",
+                    help="batch: only this case (rmat22 or er22_d16, with a root count), in the default launch "
+                         "form only, e.g. rmat22:64 (for a kernel trace of one case)")
     ap.add_argument("--rates", default="1000,5000,10000,20000,50000", help="serve: arrival rates (queries/s)")
     ap.add_argument("--queries", type=int, default=4000, help="serve: queries per rate")
     ap.add_argument("--warmup-queries", type=int, default=400, help="serve: leading queries left out of the stats")
@@ -358,7 +361,7 @@ def _batch_graph(name: str, seed: int):
     raise ValueError(name)
 
 
-def batch_case(args, name: str, widths, steps: int):
+def batch_case(args, name: str, widths, steps: int, other_form: bool = True):
     """Multi-source runs of the first `b` seeded roots for each width b, against
     the same roots run one at a time. Per case: the mean device time of `steps`
     batch runs (after one untimed run), aggregate GTEPS, the algorithmic bytes
@@ -390,11 +393,13 @@ def batch_case(args, name: str, widths, steps: int):
         pa = torch.empty((b, g.n), dtype=torch.int32, device="cuda")
         # The other launch form first (per-level launches when the default is
         # one persistent launch, or the reverse), for comparison only.
+        t_other = None
         form = bfs.bfs_graph_get_tunables(dg)["persistent"]
-        bfs.bfs_graph_set_tunables(dg, persistent=-form)
-        bfs.bfs_run_batch(dg, pool[:b], lv, pa)
-        t_other = sum(bfs.bfs_run_batch(dg, pool[:b], lv, pa)["device_ms"] for _ in range(steps)) / steps
-        bfs.bfs_graph_set_tunables(dg, persistent=form)
+        if other_form:
+            bfs.bfs_graph_set_tunables(dg, persistent=-form)
+            bfs.bfs_run_batch(dg, pool[:b], lv, pa)
+            t_other = sum(bfs.bfs_run_batch(dg, pool[:b], lv, pa)["device_ms"] for _ in range(steps)) / steps
+            bfs.bfs_graph_set_tunables(dg, persistent=form)
         bfs.bfs_run_batch(dg, pool[:b], lv, pa)  # warm-up
         sts = [bfs.bfs_run_batch(dg, pool[:b], lv, pa) for _ in range(steps)]
         t_ms = sum(st["device_ms"] for st in sts) / len(sts)
@@ -414,7 +419,7 @@ def batch_case(args, name: str, widths, steps: int):
                "frac": round(achieved / HBM_PEAK_GBS, 4), "runs": len(sts),
                "launch": "one cooperative launch for all levels" if form > 0 else "one launch per kernel and level",
                "tunables_from": ("autotuner, shipped cache " + shipped["key"]) if shipped else "library defaults",
-               "other_launch_form_ms": round(t_other, 3)}
+               "other_launch_form_ms": round(t_other, 3) if t_other is not None else None}
         rec["speedup"] = round(rec["batch_gteps"] / rec["one_at_a_time_gteps"], 2)
         results.append(rec)
         print(f"[bench] {rec}", file=sys.stderr, flush=True)
@@ -426,16 +431,24 @@ def batch_case(args, name: str, widths, steps: int):
 
 def bench_batch(args) -> int:
     results = []
-    for name, widths in (("rmat22", [64]), ("er22_d16", [8, 32, 64])):
-        results += batch_case(args, name, widths, max(args.steps, 1))
-    head = next(r for r in results if r["graph"] == "rmat22")
+    if args.batch_case:
+        name, _, width = args.batch_case.partition(":")
+        if name not in ("rmat22", "er22_d16") or not width.isdigit() or not 1 <= int(width) <= 64:
+            print(f"--batch-case wants rmat22:B or er22_d16:B with B in 1..64, not {args.batch_case!r}",
+                  file=sys.stderr)
+            return 2
+        results += batch_case(args, name, [int(width)], max(args.steps, 1), other_form=False)
+    else:
+        for name, widths in (("rmat22", [64]), ("er22_d16", [8, 32, 64])):
+            results += batch_case(args, name, widths, max(args.steps, 1))
+    head = results[0]
     out = {"metric": "batched multi-source GTEPS (aggregate) vs one root at a time", "value": head["batch_gteps"],
            "unit": "GTEPS", "n_gpus": 1, "steps": args.steps, "higher_is_better": True, "dtype": "int32",
            "data": "synthetic", "config": {"workload": "multi-source BFS, 64-bit bit-sliced masks; R-MAT scale 22 "
                                                        "(64 roots) and Erdos-Renyi 2^22 avg degree 16 (8/32/64 roots)"},
            "roofline": {"bound": "hbm", "achieved": head["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": head["frac"], "traffic": None,
-                        "kernel": f"bfs_run_batch ({head['launch']}), R-MAT 22, 64 roots",
+                        "kernel": f"bfs_run_batch ({head['launch']}), {head['graph']}, {head['roots']} roots",
                         "bytes_alg_per_launch": head["bytes_alg"]},
            "cases": results}
     print(json.dumps(out), flush=True)

@@ -1,9 +1,10 @@
 """Text summaries of rocprofv3 CSV output for the BFS kernels.
 
     python -m paper_1604_02844_amd.profsum trace DIR --runs N [--title T] [--command C]
+                                                  [--kernels K1,K2,...] [--unit U]
         per-kernel calls, total and average duration from the kernel trace
         (rocprofv3 --kernel-trace --stats --output-format csv -d DIR), and the
-        kernel time per BFS run.
+        kernel time per BFS run (or per U, over the kernels K).
     python -m paper_1604_02844_amd.profsum traffic FETCH_DIR WRITE_DIR --runs N --copy-bytes B ...
         HBM traffic per BFS run from two counter passes (--pmc FETCH_SIZE, then
         --pmc WRITE_SIZE), each scaled by what the same counter reads for the
@@ -103,21 +104,25 @@ def read_counter(root: str, counter: str) -> dict[str, list[float]]:
 
 def cmd_trace(a) -> None:
     tr = read_trace(a.dir)
+    kernels = tuple(k for k in a.kernels.split(",") if k) if a.kernels else RUN_KERNELS
+    unit = a.unit
     lines = [f"# {a.title}", "", f"Command: `{a.command}`", "", f"Summary: `{_self_command()}`", "",
              f"Library source digest: {source_digest()}",
-             f"BFS runs in the trace: {a.runs}", "",
+             f"{unit[0].upper() + unit[1:]}{'es' if unit.endswith(('s', 'x', 'ch', 'sh')) else 's'} in the trace: "
+             f"{a.runs}", "",
              "| kernel | calls | total ms | avg us | min us | max us |", "|---|---|---|---|---|---|"]
     total_run = 0.0
     for k, d in sorted(tr.items(), key=lambda kv: -sum(kv[1])):
         tot = sum(d)
-        if k in RUN_KERNELS:
+        if k in kernels:
             total_run += tot
         lines.append(f"| {k} | {len(d)} | {tot / 1e6:.3f} | {tot / len(d) / 1e3:.2f} | {min(d) / 1e3:.2f} | "
                      f"{max(d) / 1e3:.2f} |")
-    lines += ["", f"Kernel time per BFS run ({' + '.join(RUN_KERNELS)}): {total_run / a.runs / 1e6:.4f} ms"]
-    for k in RUN_KERNELS:
+    lines += ["", f"Kernel time per {unit} ({' + '.join(kernels)}): {total_run / a.runs / 1e6:.4f} ms"]
+    for k in kernels:
         if k in tr:
-            lines.append(f"  {k}: {sum(tr[k]) / a.runs / 1e6:.4f} ms per run, {len(tr[k]) / a.runs:.1f} launches per run")
+            lines.append(f"  {k}: {sum(tr[k]) / a.runs / 1e6:.4f} ms per {unit}, "
+                         f"{len(tr[k]) / a.runs:.1f} launches per {unit}")
     print("\n".join(lines))
 
 
@@ -181,6 +186,8 @@ def main(argv=None) -> int:
     t.add_argument("--runs", type=int, required=True)
     t.add_argument("--title", default="Kernel trace")
     t.add_argument("--command", default="")
+    t.add_argument("--kernels", default="", help="comma-separated kernels counted per unit (default: a bfs_run's)")
+    t.add_argument("--unit", default="BFS run", help="what --runs counts, for the labels")
     c = sub.add_parser("traffic")
     c.add_argument("fetch_dir")
     c.add_argument("write_dir")

@@ -127,7 +127,10 @@ typedef struct {
                                    is expanded by the expansion kernel's first workgroup alone,
                                    from the list of the frontier the previous restoration made,
                                    with exact atomicOr claims; consecutive such levels run in
-                                   that one launch. -1 = off, 0 = library default (1024) */
+                                   that one launch. On, it reserves 80 KiB of the expansion's LDS
+                                   (within the 128 KiB the hot bitmap takes by default; smaller
+                                   workgroups without the hot bitmap then fit fewer per CU).
+                                   -1 = off, 0 = library default (1024) */
     int32_t block_vertices;     /* single-root runs on the degree-ordered copy: rows above T2
                                    keep their arcs grouped by destination block of this many
                                    vertices (a power of two from 2^11 to 2^20, rounded down), and

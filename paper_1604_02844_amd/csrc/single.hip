@@ -34,15 +34,18 @@
 //              next frontier bitmap, per-level discovered count, and the list
 //              of the next frontier's big rows: one segment per restore block,
 //              placed with a workgroup prefix sum (no atomics).
-// Levels are enqueued in chunks; the host reads a done flag between chunks.
+// A small frontier (tunable sparse_frontier) is expanded by k_expand's first
+// workgroup alone, which goes on through the small levels after it in the
+// same launch (small_levels). Levels are enqueued in chunks; the host reads a
+// done flag between chunks.
 //
-// Coherence: the eight XCDs have private L2 caches, so a plain load in one
-// launch may return a line that another XCD rewrote in an earlier launch. All
-// state that crosses launches (levels, visited snapshot, frontier, counters,
-// big-row list) is therefore read with device-scope loads, except the per-arc
-// visited probe: it stays a plain load used only as a filter, and a candidate
-// it lets through is confirmed on the level array with a device-scope load
-// before it is claimed.
+// Coherence: the eight XCDs have private L2 caches. Launch boundaries make
+// them agree (a plain load sees what another XCD wrote in an earlier launch),
+// but within a launch an XCD's L2 does not see other XCDs' stores. Shared state
+// is read and written with device-scope accesses; the per-arc visited probe is
+// a plain load used only as a filter, and a candidate it lets through is
+// confirmed on the level array with a device-scope load, which sees claims that
+// other XCDs made earlier in the same launch, before it is claimed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

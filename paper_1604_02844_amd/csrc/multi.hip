@@ -64,9 +64,11 @@ struct MsParams {
     int32_t t1;
 };
 
-// Cross-kernel shared state (masks, statistics, slot table) is accessed with
-// device-scope loads and stores: each XCD has its own L2, and a plain load may
-// otherwise hit a line another XCD rewrote in an earlier kernel.
+// Shared state (masks, statistics, slot table) is accessed with device-scope
+// loads and stores. Launch boundaries make the XCDs' L2 caches agree, so for
+// state written only by earlier launches plain loads would do as well (the
+// pull's neighbour masks read either way took the same time); within a launch
+// each XCD's L2 does not see the others' stores, and device scope does.
 template <typename T>
 __device__ __forceinline__ T ld(const T* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -47,6 +47,15 @@ constexpr int kPullHead = 32;  // arcs a lane scans on its own before its wavefr
 // 3.01; 3: 7.34, 8.25, 3.28; 2: 7.40, 8.29, 3.33; 1: 21.4, 27.5, 5.86.
 constexpr int kPushAlpha = 4;
 
+// The slot table (output rows and start levels), copied into LDS by every
+// workgroup of a level kernel, so that a discovery reads its row pointers
+// from LDS instead of the control block.
+struct SlotTable {
+    int32_t* lv[64];
+    int32_t* pa[64];
+    int32_t start[64];
+};
+
 struct MsParams {
     const void* off;
     const int32_t* col;
@@ -62,6 +71,7 @@ struct MsParams {
     int32_t num_big;
     int64_t big_arcs;
     int32_t t1;
+    const SlotTable* slots;  // set inside the kernels to the LDS copy
 };
 
 // Shared state (masks, statistics, slot table) is accessed with device-scope
@@ -155,12 +165,22 @@ __device__ __forceinline__ bool choose_push(const MsParams& p, const LevelView& 
 }
 
 // Record the discovery of vertex v by the roots in nb, with parent u.
-__device__ __forceinline__ void record(MsCtrl* c, int32_t v, int32_t u, u64 nb, int lvl) {
+__device__ __forceinline__ void record(const SlotTable& t, int32_t v, int32_t u, u64 nb, int lvl) {
     while (nb) {
         const int i = __builtin_ctzll(nb);
         nb &= nb - 1;
-        ld(&c->out_lv[i])[v] = lvl + 1 - ld(&c->start[i]);
-        ld(&c->out_pa[i])[v] = u;
+        t.lv[i][v] = lvl + 1 - t.start[i];
+        t.pa[i][v] = u;
+    }
+}
+
+// Copy of the slot table into LDS (threads 0..63; the caller synchronises).
+__device__ __forceinline__ void load_slots(MsCtrl* c, SlotTable& t) {
+    const int i = threadIdx.x;
+    if (i < 64) {
+        t.lv[i] = ld(&c->out_lv[i]);
+        t.pa[i] = ld(&c->out_pa[i]);
+        t.start[i] = ld(&c->start[i]);
     }
 }
 
@@ -188,7 +208,7 @@ __device__ __forceinline__ void push_arcs(const MsParams& p, const int64_t (&pos
         const u64 nb = t[i] & ~old[i];
         if (nb) {
             atomicOr(p.nfr + v[i], nb);
-            record(p.ctrl, v[i], par[i], nb, lvl);
+            record(*p.slots, v[i], par[i], nb, lvl);
         }
     }
 }
@@ -381,9 +401,12 @@ __device__ __forceinline__ void push_level(const MsParams& p, int lvl, u64 alive
 template <typename OffT, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_ms_push(MsParams p, int lvl) {
     __shared__ PushShared<BLOCK> sh;
+    __shared__ SlotTable slots;
     if (ld(&p.ctrl->done)) return;
+    load_slots(p.ctrl, slots);  // synchronised by begin_level's barrier
     const LevelView lv = begin_level(p, lvl);
     if (lv.disc == 0 || !choose_push(p, lv)) return;
+    p.slots = &slots;
     push_level<OffT, BLOCK>(p, lvl, lv.alive, sh);
 }
 
@@ -444,7 +467,7 @@ __device__ __forceinline__ void pull_level(const MsParams& p, int lvl, u64 alive
                     while (b) {
                         const int i = __builtin_ctzll(b);
                         b &= b - 1;
-                        ld(&p.ctrl->out_pa[i])[v] = u[q];
+                        p.slots->pa[i][v] = u[q];
                     }
                 }
             }
@@ -465,7 +488,7 @@ __device__ __forceinline__ void pull_level(const MsParams& p, int lvl, u64 alive
                 const u64 f = ld(p.fr + u);
                 const u64 nb = in_row ? (f & m & ~a) : 0ull;
                 const u64 mine = nb & ~wave_excl_or(nb, lane);
-                for (u64 b = mine; b; b &= b - 1) ld(&p.ctrl->out_pa[__builtin_ctzll(b)])[vs] = u;
+                for (u64 b = mine; b; b &= b - 1) p.slots->pa[__builtin_ctzll(b)][vs] = u;
                 a |= wave_or(nb);
             }
             if (lane == src) acc = a;
@@ -478,7 +501,7 @@ __device__ __forceinline__ void pull_level(const MsParams& p, int lvl, u64 alive
                 while (b) {
                     const int i = __builtin_ctzll(b);
                     b &= b - 1;
-                    ld(&p.ctrl->out_lv[i])[v] = lvl + 1 - ld(&p.ctrl->start[i]);
+                    p.slots->lv[i][v] = lvl + 1 - p.slots->start[i];
                 }
             }
         }
@@ -487,9 +510,12 @@ __device__ __forceinline__ void pull_level(const MsParams& p, int lvl, u64 alive
 
 template <typename OffT>
 __global__ __launch_bounds__(256) void k_ms_pull(MsParams p, int lvl) {
+    __shared__ SlotTable slots;
     if (ld(&p.ctrl->done)) return;
+    load_slots(p.ctrl, slots);  // synchronised by read_level's barrier
     const LevelView lview = read_level(p.ctrl, lvl);
     if (lview.disc == 0 || choose_push(p, lview)) return;
+    p.slots = &slots;
     pull_level<OffT>(p, lvl, lview.alive);
 }
 
@@ -582,7 +608,10 @@ template <typename OffT>
 __global__ __launch_bounds__(256) void k_ms_batch(MsParams p, u64* fr0, u64* fr1, int max_levels) {
     __shared__ PushShared<256> sh;
     __shared__ u64 red[4][4];
+    __shared__ SlotTable slots;
     cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+    load_slots(p.ctrl, slots);  // synchronised by begin_level's barrier
+    p.slots = &slots;
     for (int lvl = 0; lvl < max_levels; ++lvl) {
         p.fr = (lvl & 1) ? fr1 : fr0;
         p.nfr = (lvl & 1) ? fr0 : fr1;

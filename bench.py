@@ -163,6 +163,13 @@ def main() -> int:
               "(batched and served BFS would shard by replicating each graph on every GPU)",
               file=sys.stderr)
         return 2
+    if args.batch_case:
+        name, _, width = args.batch_case.partition(":")
+        if args.mode != "batch" or name not in ("rmat22", "er22_d16") or not width.isdigit() or \
+                not 1 <= int(width) <= 64:
+            print(f"--batch-case wants --mode batch and rmat22:B or er22_d16:B with B in 1..64, "
+                  f"not {args.batch_case!r}", file=sys.stderr)
+            return 2
 
     import torch
 
@@ -431,12 +438,8 @@ def batch_case(args, name: str, widths, steps: int, other_form: bool = True):
 
 def bench_batch(args) -> int:
     results = []
-    if args.batch_case:
+    if args.batch_case:  # checked in main
         name, _, width = args.batch_case.partition(":")
-        if name not in ("rmat22", "er22_d16") or not width.isdigit() or not 1 <= int(width) <= 64:
-            print(f"--batch-case wants rmat22:B or er22_d16:B with B in 1..64, not {args.batch_case!r}",
-                  file=sys.stderr)
-            return 2
         results += batch_case(args, name, [int(width)], max(args.steps, 1), other_form=False)
     else:
         for name, widths in (("rmat22", [64]), ("er22_d16", [8, 32, 64])):

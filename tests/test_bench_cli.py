@@ -24,3 +24,12 @@ def test_world_size_above_one_is_refused():
     r = run_bench(env=env)
     assert r.returncode == 2
     assert "exactly one GPU" in r.stderr
+
+
+def test_bad_batch_case_is_refused():
+    for bad in (["--mode", "batch", "--batch-case", "rmat99:64"], ["--mode", "batch", "--batch-case", "rmat22:65"],
+                ["--mode", "batch", "--batch-case", "rmat22"], ["--batch-case", "rmat22:64"]):
+        r = run_bench(*bad)
+        assert r.returncode == 2, bad
+        assert "--batch-case wants" in r.stderr
+        assert r.stdout == ""
